@@ -1,0 +1,414 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: worked
+examples (tests/golden), closed forms of Eq. 1 and Eq. 6, invariants
+(weights summing to one, partition of unity, occlusion, permutation),
+a brute-force per-pixel re-derivation, and exact finite differences.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests import brute_force
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cam_of(d):
+    return workloads.Camera(R=np.asarray(d["R"], np.float32).reshape(3, 3),
+                            t=np.asarray(d["t"], np.float32), fx=d["fx"], fy=d["fy"],
+                            cx=d["cx"], cy=d["cy"], width=d["width"], height=d["height"],
+                            near=d.get("near", 0.01), far=d.get("far", 100.0))
+
+
+def ident_cam(W=16, H=16, f=1.0, c=0.0, near=0.01, far=100.0):
+    return workloads.Camera(R=np.eye(3, dtype=np.float32), t=np.zeros(3, np.float32), fx=f, fy=f,
+                            cx=c, cy=c, width=W, height=H, near=near, far=far)
+
+
+def centre_point(x, y, z=1.0):
+    """World point landing on the centre of pixel (x, y) of ident_cam (f=1, c=0, z=1)."""
+    return [x + 0.5, y + 0.5, z]
+
+
+def f32bits(x):
+    return int(np.asarray(x, np.float32).view(np.uint32))
+
+
+# --------------------------------------------------------------------- constants
+def test_paper_constants_match_workload_defaults():
+    c = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert workloads.scenes.TAU == c["transmittance_threshold"]["value"]
+    assert workloads.scenes.NEAR == c["near_plane"]["value"]
+    assert workloads.scenes.FAR == c["far_plane"]["value"]
+
+
+# --------------------------------------------------------------- O1: projection
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "hand_projection.json")))["cases"],
+                         ids=lambda c: c["name"])
+def test_hand_worked_projection(case):
+    cam = cam_of(case["camera"])
+    xyz = np.asarray([case["xyz"]], np.float32)
+    pix, zb, ids, w = oracle.emit(xyz, cam)
+    W = case["camera"]["width"]
+    got = sorted(zip(pix.tolist(), ids.tolist(), w.tolist()))
+    exp = sorted((f["pixel"][1] * W + f["pixel"][0], f["corner"], f["weight"]) for f in case["fragments"])
+    assert got == exp
+    assert all(z == f32bits(np.float32(case["xyz"][2]) + np.float32(case["camera"]["t"][2])) for z in zb)
+
+
+def test_pixel_centre_lands_wholly_in_that_pixel():
+    rng = np.random.default_rng(5)
+    W = H = 16
+    xs, ys = rng.integers(0, W, 50), rng.integers(0, H, 50)
+    xyz = np.asarray([centre_point(x, y) for x, y in zip(xs, ys)], np.float32)
+    pix, zb, ids, w = oracle.emit(xyz, ident_cam(W, H))
+    assert len(pix) == 50
+    assert np.all(w == 1.0)
+    assert np.all(pix == ys * W + xs)
+    assert np.all(ids == 4 * np.arange(50))   # corner 0 of each point
+
+
+def test_interior_weights_sum_to_one_exactly():
+    # u, v at least one pixel away from the top/left border: 1-a is exact in float32
+    rng = np.random.default_rng(6)
+    W, H = 64, 48
+    n = 2000
+    xyz = np.stack([rng.uniform(2, W - 2, n), rng.uniform(2, H - 2, n), np.ones(n)], 1).astype(np.float32)
+    pix, zb, ids, w = oracle.emit(xyz, ident_cam(W, H))
+    p = ids >> 2
+    sums = np.bincount(p, weights=w, minlength=n)
+    counts = np.bincount(p, minlength=n)
+    assert np.all(sums == 1.0)
+    # four splats unless the point sits exactly on a centre row/column
+    su = xyz[:, 0] - np.float32(0.5)
+    sv = xyz[:, 1] - np.float32(0.5)
+    on_col = (su - np.floor(su)) == 0
+    on_row = (sv - np.floor(sv)) == 0
+    exp = np.where(on_col, 1, 2) * np.where(on_row, 1, 2)
+    assert np.array_equal(counts, exp)
+
+
+def test_weights_match_eq6_distances():
+    # alpha factor of pixel i is (1-|u-u_i|)(1-|v-v_i|) with u_i the pixel centre
+    rng = np.random.default_rng(7)
+    W, H = 32, 32
+    xyz = np.stack([rng.uniform(0, W, 500), rng.uniform(0, H, 500), np.ones(500)], 1).astype(np.float32)
+    pix, zb, ids, w = oracle.emit(xyz, ident_cam(W, H))
+    p = ids >> 2
+    u = xyz[p, 0].astype(np.float64)
+    v = xyz[p, 1].astype(np.float64)
+    cx = (pix % W) + 0.5
+    cy = (pix // W) + 0.5
+    assert np.all(np.abs(u - cx) < 1) and np.all(np.abs(v - cy) < 1)
+    ref = (1 - np.abs(u - cx)) * (1 - np.abs(v - cy))
+    assert np.allclose(w, ref, rtol=0, atol=1e-6)
+
+
+def test_border_points_keep_only_in_image_corners():
+    W, H = 16, 16
+    pts = [[0.25, 8.5, 1], [15.75, 8.5, 1], [8.5, 0.25, 1], [8.5, 15.75, 1], [0.25, 0.25, 1],
+           [15.75, 15.75, 1]]
+    pix, zb, ids, w = oracle.emit(np.asarray(pts, np.float32), ident_cam(W, H))
+    got = sorted(zip((ids >> 2).tolist(), pix.tolist(), w.tolist()))
+    exp = sorted([(0, 8 * W + 0, 0.75), (1, 8 * W + 15, 0.75), (2, 0 * W + 8, 0.75), (3, 15 * W + 8, 0.75),
+                  (4, 0, 0.5625), (5, 15 * W + 15, 0.5625)])
+    assert got == exp
+
+
+def test_culling_near_far_guard_and_nonfinite():
+    W, H = 16, 16
+    cam = ident_cam(W, H, near=0.5, far=10.0)
+    pts = [[1.0, 1.0, 0.5],            # z == near: culled (strict)
+           [1.0, 1.0, 10.0],           # z == far: culled
+           [1.0, 1.0, -2.0],           # behind
+           [float("nan"), 1.0, 2.0],
+           [float("inf"), 1.0, 2.0],
+           [1.0, 1.0, float("nan")],
+           [-2.2, 2.0, 2.0],           # u = -1.1: outside the guard
+           [34.2, 2.0, 2.0],           # u = 17.1: outside
+           [-1.2, 2.0, 2.0],           # u = -0.6: inside the guard but both columns off-image
+           [1.0, 1.0, 0.5000001]]      # just inside the near plane: kept
+    pix, zb, ids, w = oracle.emit(np.asarray(pts, np.float32), cam)
+    assert set((ids >> 2).tolist()) == {9}
+
+
+def test_depth_bits_order_equals_float_order():
+    z = np.sort(np.random.default_rng(0).uniform(0.011, 99.0, 10000).astype(np.float32))
+    b = z.view(np.uint32)
+    assert np.all(np.diff(b.astype(np.int64)) >= 0)
+
+
+# ------------------------------------------------------- O2: lists and order
+def _random_tiny_scene(seed, n=120, W=12, H=10, dup=True):
+    rng = np.random.default_rng(seed)
+    cam = workloads.look_at_camera(rng.uniform(-0.2, 0.2, 3), (0, 0, 4), (0, -1, 0), W, H, 70.0)
+    xyz = rng.uniform(-1.5, 1.5, (n, 3)) + np.array([0, 0, 4.0])
+    if dup:
+        xyz[n // 2: n // 2 + 10] = xyz[:10]   # exact duplicates: equal depth, ids decide
+    xyz[-3] = [np.nan, 0, 4]
+    feat = rng.uniform(0, 1, (n, 3))
+    opa = rng.uniform(0.05, 0.95, n)
+    opa[5] = 1.0
+    opa[6] = 0.0
+    return xyz.astype(np.float32), feat.astype(np.float32), opa.astype(np.float32), cam
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("tau", [1e-4, 0.0, 0.3])
+def test_oracle_matches_brute_force(seed, tau):
+    xyz, feat, opa, cam = _random_tiny_scene(seed)
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, tau)
+    b = brute_force.render(xyz, feat, opa, cam, tau)
+    assert np.array_equal(L.keys(), b["keys"])
+    assert np.array_equal(L.ids, b["ids"])
+    assert np.array_equal(o["n_blended"], b["n_blended"])
+    assert np.allclose(o["image"], b["image"], rtol=1e-13, atol=1e-15)
+    assert np.allclose(o["t_final"], b["t_final"], rtol=1e-13, atol=1e-15)
+
+
+def test_sorted_keys_and_multiset():
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    k = L.keys()
+    order = np.lexsort((L.ids, k))
+    assert np.array_equal(order, np.arange(L.m))
+    pix, zb, ids, w = oracle.emit(s.xyz, s.cam)
+    assert np.array_equal(np.sort(ids), np.sort(L.ids))
+    emitted = (pix.astype(np.uint64) << np.uint64(32)) | zb.astype(np.uint64)
+    assert np.array_equal(np.sort(emitted), np.sort(k))
+
+
+def test_duplicates_ordered_by_ascending_id():
+    W = H = 8
+    xyz = np.asarray([[3.3, 4.1, 2.0]] * 5, np.float32) * np.asarray([1, 1, 1], np.float32)
+    L = oracle.fragments(xyz, ident_cam(W, H, f=2.0))
+    for q in range(L.P):
+        seg = L.ids[L.start[q]:L.start[q + 1]]
+        assert np.all(np.diff(seg.astype(np.int64)) > 0)
+    assert L.m > 0
+
+
+def test_permuting_points_permutes_ids_only():
+    s = workloads.config1()
+    perm = np.random.default_rng(3).permutation(s.n)
+    L0 = oracle.fragments(s.xyz, s.cam)
+    L1 = oracle.fragments(s.xyz[perm], s.cam)
+    o0 = oracle.blend_forward(L0, s.opa, s.feat, 1e-4)
+    o1 = oracle.blend_forward(L1, s.opa[perm], s.feat[perm], 1e-4)
+    # depths are distinct in config 1, so lists keep their order and images are bit-identical
+    assert np.array_equal(o0["image"], o1["image"])
+    assert np.array_equal(o0["t_final"], o1["t_final"])
+    mapped = 4 * perm[L1.ids >> 2] + (L1.ids & 3)   # point j of the permuted cloud is point perm[j]
+    assert np.array_equal(mapped.astype(np.uint32), L0.ids)
+
+
+# ------------------------------------------------------------ O3: blending
+def _stack(pixel_xy, depths, opas, feats, W=8, H=8):
+    """Points stacked on the centre of one pixel at the given depths (one splat each, w = 1)."""
+    x, y = pixel_xy
+    f = 2.0
+    xyz = np.asarray([[(x + 0.5) * d / f, (y + 0.5) * d / f, d] for d in depths], np.float32)
+    cam = ident_cam(W, H, f=f)
+    return xyz, np.asarray(feats, np.float32), np.asarray(opas, np.float32), cam
+
+
+def test_stack_points_are_single_full_weight_splats():
+    xyz, feat, opa, cam = _stack((3, 2), [1.0, 2.0, 4.0], [0.5] * 3, [[1]] * 3)
+    pix, zb, ids, w = oracle.emit(xyz, cam)
+    assert np.all(pix == 2 * 8 + 3) and np.all(w == 1.0) and len(pix) == 3
+
+
+def test_single_splat_closed_form():
+    xyz, feat, opa, cam = _stack((1, 1), [2.0], [0.3], [[0.25, 0.75]])
+    o = oracle.render(xyz, feat, opa, cam)
+    q = 1 * 8 + 1
+    assert np.allclose(o["image"].reshape(-1, 2)[q], [np.float32(0.3) * 0.25, np.float32(0.3) * 0.75], rtol=1e-15)
+    assert o["t_final"].reshape(-1)[q] == 1 - np.float64(np.float32(0.3))
+    assert o["n_blended"][q] == 1
+    others = np.delete(np.arange(64), q)
+    assert np.all(o["image"].reshape(-1, 2)[others] == 0) and np.all(o["t_final"].reshape(-1)[others] == 1)
+
+
+def test_two_splats_closed_form_and_gradients():
+    af, ab, cf, cb = 0.375, 0.625, 0.5, 0.25   # exact in float32
+    # back point listed first in the input: order must come from depth
+    xyz, feat, opa, cam = _stack((4, 5), [3.0, 1.5], [ab, af], [[cb], [cf]])
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, 1e-4)
+    q = 5 * 8 + 4
+    assert o["image"][q, 0] == af * cf + (1 - af) * ab * cb
+    assert o["t_final"][q] == (1 - af) * (1 - ab)
+    g = np.zeros((64, 1), np.float32)
+    g[q, 0] = 1.0
+    gt = np.zeros(64, np.float32)
+    gb = oracle.blend_backward(L, opa, feat, o["n_blended"], g, gt)
+    # point 1 is the front one
+    assert gb["grad_opa"][1] == cf - ab * cb
+    assert gb["grad_opa"][0] == (1 - af) * cb
+    assert gb["grad_feat"][1, 0] == af
+    assert gb["grad_feat"][0, 0] == (1 - af) * ab
+    gt[q] = 1.0
+    g[:] = 0
+    gb = oracle.blend_backward(L, opa, feat, o["n_blended"], g, gt)
+    assert gb["grad_opa"][1] == -(1 - ab)
+    assert gb["grad_opa"][0] == -(1 - af)
+
+
+def test_opaque_front_point_occludes_everything_behind():
+    depths = [1.0, 2.0, 3.0, 5.0]
+    xyz, feat, opa, cam = _stack((2, 6), depths, [1.0, 0.7, 0.4, 0.9], [[0.3, 0.6], [1, 1], [1, 0], [0, 1]])
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, 1e-4)
+    q = 6 * 8 + 2
+    assert o["image"][q].tolist() == [np.float64(np.float32(0.3)), np.float64(np.float32(0.6))]
+    assert o["t_final"][q] == 0.0 and o["n_blended"][q] == 1
+    o0 = oracle.blend_forward(L, opa, feat, 0.0)          # no termination: everything blended
+    assert o0["n_blended"][q] == 4 and o0["image"][q].tolist() == o["image"][q].tolist()
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=(64, 2)).astype(np.float32)
+    for nb in (o["n_blended"], o0["n_blended"]):
+        gb = oracle.blend_backward(L, opa, feat, nb, g, rng.normal(size=64).astype(np.float32))
+        assert np.all(gb["grad_feat"][1:] == 0) and np.all(gb["grad_opa"][1:] == 0)
+
+
+@pytest.mark.parametrize("tau", [1e-4, 0.0])
+def test_partition_of_unity(tau):
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    o = oracle.blend_forward(L, s.opa, np.ones((s.n, 1), np.float32), tau)
+    assert np.allclose(o["image"][:, 0] + o["t_final"], 1.0, rtol=0, atol=1e-14)
+
+
+def test_linearity_in_features():
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    rng = np.random.default_rng(1)
+    # multiples of 2^-8, so the combination below is exact in float32
+    f1 = (rng.integers(0, 256, (s.n, 4)) / 256.0).astype(np.float32)
+    f2 = (rng.integers(0, 256, (s.n, 4)) / 256.0).astype(np.float32)
+    a, b = 0.25, 2.0
+    comb = (a * f1.astype(np.float64) + b * f2.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(comb.astype(np.float64), a * f1.astype(np.float64) + b * f2.astype(np.float64))
+    o1 = oracle.blend_forward(L, s.opa, f1, 1e-4)["image"]
+    o2 = oracle.blend_forward(L, s.opa, f2, 1e-4)["image"]
+    oc = oracle.blend_forward(L, s.opa, comb, 1e-4)["image"]
+    assert np.allclose(oc, a * o1 + b * o2, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("alpha", [0.1, 0.3, 0.55, 0.8])
+def test_equal_splats_terminate_at_first_n_below_tau(alpha):
+    tau = 1e-4
+    k = 100
+    xyz, feat, opa, cam = _stack((0, 0), [1.0 + 0.05 * i for i in range(k)], [alpha] * k, [[1.0]] * k)
+    o = oracle.render(xyz, feat, opa, cam, tau)
+    a = float(np.float32(alpha))
+    n_exp = math.ceil(math.log(tau) / math.log(1 - a))
+    assert abs(n_exp - math.log(tau) / math.log(1 - a)) > 1e-6   # not on a rounding boundary
+    assert n_exp < k
+    assert o["n_blended"][0] == n_exp
+    assert o["t_final"].reshape(-1)[0] < tau
+    assert o["t_final"].reshape(-1)[0] == pytest.approx((1 - a) ** n_exp, rel=1e-12)
+
+
+def test_tau_zero_blends_every_splat():
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    o = oracle.blend_forward(L, s.opa, s.feat, 0.0)
+    assert np.array_equal(o["n_blended"], np.diff(L.start).astype(np.int32))
+
+
+def test_bf16_features_are_widened_exactly():
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    bits = (s.feat.view(np.uint32) >> 16).astype(np.uint16)       # truncation: any bf16 pattern
+    widened = (bits.astype(np.uint32) << 16).view(np.float32)
+    a = oracle.blend_forward(L, s.opa, bits, 1e-4)
+    b = oracle.blend_forward(L, s.opa, widened, 1e-4)
+    assert np.array_equal(a["image"], b["image"])
+
+
+# ---------------------------------------------------------- O4/O5: backward
+def _loss(L, opa, feat, nb, g, gt):
+    o = oracle.blend_forward(L, opa, feat, 0.0, n_override=nb)
+    return float(np.sum(o["image"] * g) + np.sum(o["t_final"] * gt))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_backward_matches_central_differences(seed):
+    # L is affine in each point's alpha_h and features when n_blended is held
+    # fixed (a point has at most one splat per pixel), so central differences
+    # are exact up to rounding.
+    xyz, feat, opa, cam = _random_tiny_scene(seed, n=80, W=10, H=9)
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, 1e-4)
+    rng = np.random.default_rng(seed + 10)
+    F = feat.shape[1]
+    g = rng.normal(size=(L.P, F)).astype(np.float32)
+    gt = rng.normal(size=L.P).astype(np.float32)
+    gb = oracle.blend_backward(L, opa, feat, o["n_blended"], g, gt)
+    # the oracle takes float32 inputs: perturb by exactly representable steps
+    h = 2.0 ** -12
+    for p in range(xyz.shape[0]):
+        op, om = opa.copy(), opa.copy()
+        op[p] += np.float32(h)
+        om[p] -= np.float32(h)
+        fd = (_loss(L, op, feat, o["n_blended"], g, gt) - _loss(L, om, feat, o["n_blended"], g, gt)) / \
+             (float(op[p]) - float(om[p]))
+        assert fd == pytest.approx(gb["grad_opa"][p], rel=1e-9, abs=1e-11)
+        c = p % F
+        fp, fm = feat.copy(), feat.copy()
+        fp[p, c] += np.float32(h)
+        fm[p, c] -= np.float32(h)
+        fd = (_loss(L, opa, fp, o["n_blended"], g, gt) - _loss(L, opa, fm, o["n_blended"], g, gt)) / \
+             (float(fp[p, c]) - float(fm[p, c]))
+        assert fd == pytest.approx(gb["grad_feat"][p, c], rel=1e-9, abs=1e-11)
+
+
+def test_backward_dot_product_identity_features():
+    # image is jointly linear in all features: <g, J d> = <J^T g, d> exactly
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    o = oracle.blend_forward(L, s.opa, s.feat, 1e-4)
+    rng = np.random.default_rng(2)
+    g = rng.normal(size=(L.P, 4)).astype(np.float32)
+    d = rng.normal(size=(s.n, 4)).astype(np.float32)
+    gb = oracle.blend_backward(L, s.opa, s.feat, o["n_blended"], g, None)
+    Jd = oracle.blend_forward(L, s.opa, d, 0.0, n_override=o["n_blended"])["image"]
+    lhs = float(np.sum(g.astype(np.float64) * Jd))
+    rhs = float(np.sum(gb["grad_feat"] * d))
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_backward_dot_product_identity_opacity():
+    s = workloads.config1()
+    L = oracle.fragments(s.xyz, s.cam)
+    o = oracle.blend_forward(L, s.opa, s.feat, 1e-4)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(L.P, 4)).astype(np.float32)
+    gt = rng.normal(size=L.P).astype(np.float32)
+    d = rng.normal(size=s.n)
+    gb = oracle.blend_backward(L, s.opa, s.feat, o["n_blended"], g, gt)
+    h = 2.0 ** -20
+    op = (s.opa.astype(np.float64) + h * d).astype(np.float32)
+    om = (s.opa.astype(np.float64) - h * d).astype(np.float32)
+    dd = (op.astype(np.float64) - om.astype(np.float64)) / 2
+    fd = (_loss(L, op, s.feat, o["n_blended"], g, gt) - _loss(L, om, s.feat, o["n_blended"], g, gt)) / 2
+    assert fd == pytest.approx(float(np.sum(gb["grad_opa"] * dd)), rel=1e-6)
+
+
+def test_unsplatted_points_get_exact_zero_gradient():
+    xyz, feat, opa, cam = _random_tiny_scene(4)
+    xyz[:7, 2] = -5.0                                   # behind the camera
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, 1e-4)
+    rng = np.random.default_rng(0)
+    gb = oracle.blend_backward(L, opa, feat, o["n_blended"], rng.normal(size=(L.P, 3)).astype(np.float32))
+    assert np.all(gb["grad_feat"][:7] == 0) and np.all(gb["grad_opa"][:7] == 0)
