@@ -1,0 +1,222 @@
+/*
+ * inpc_raster.h -- C ABI of the MI355X (gfx950) differentiable bilinear point
+ * rasterizer of INPC (Implicit Neural Point Clouds, arXiv 2403.16862).
+ *
+ * The operation (Appendix A.6, Algorithm 1, "Rasterize(C, P, A, F) -> I"):
+ *   1. project every point with the camera (Section 3.4, Eq. 5) and cull it
+ *      against the near/far planes and the image;
+ *   2. splat it to the 2x2 pixels whose centres are closest to (u, v) with
+ *      opacity alpha = alpha_h (1-|u-u_i|)(1-|v-v_i|) (Section 3.4, Eq. 6);
+ *   3. order each pixel's splats by depth with one global sort of
+ *      (pixel, depth) keys;
+ *   4. blend each pixel front to back, C = sum_i T_i alpha_i c_i,
+ *      T_i = prod_{j<i} (1 - alpha_j) (Eq. 1), stopping after the splat that
+ *      drops T below the threshold (Appendix A.6: 1e-4);
+ *   5. backward: per-splat gradients in forward order, combined per point as
+ *      a bilinear-weighted sum of its splat gradients (Appendix A.6).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_host are host memory; every other array pointer is
+ *     device memory on the current HIP device.  All device memory is owned by
+ *     the caller; the library never allocates device memory in these calls.
+ *   - Work is enqueued on ``stream`` (a hipStream_t; NULL = default stream)
+ *     and the call returns without synchronising, so the calls can be
+ *     captured in a HIP graph.  Outputs are valid once the stream reaches
+ *     that point.
+ *   - Arguments are validated on the host before anything is enqueued; on
+ *     error nothing is enqueued and a negative INPC_E* code is returned.
+ *     Per-element preconditions (opacity in [0,1], finite features) are not
+ *     checked.
+ *   - Layouts: xyz float32 [N,3] row-major; features [N,F] row-major in
+ *     float32 or bfloat16 (``feat_dtype``); opacity float32 [N] (the activated
+ *     alpha_h); image float32 [H,W,F]; t_final float32 [H,W] (the remaining
+ *     transmittance, so alpha = 1 - t_final).  Gradients are always float32.
+ *   - Camera: x_c = R x + t (R row-major), u = fx x_c/z_c + cx,
+ *     v = fy y_c/z_c + cy; pixel (x,y) covers [x,x+1) x [y,y+1) and has its
+ *     centre at (x+0.5, y+0.5).  A point is kept iff near < z_c < far and
+ *     -1 < u < W+1, -1 < v < H+1.  Splats outside the image or with a zero
+ *     bilinear factor are dropped and the rest are not renormalised.
+ *     Equal depths in one pixel are ordered by ascending point index.
+ *   - Limits: 1 <= F <= 64; 1 <= width, height <= 16383; total points over
+ *     all views < 2^28; total pixels over all views < 2^32 - 1.
+ *   - No gradient flows to positions or cameras (INPC samples positions
+ *     rather than optimising them, Section 3.2).
+ *   - The library keeps no state between calls except the autotuner's cache
+ *     (guarded by a mutex); all entry points are reentrant.
+ */
+#ifndef INPC_RASTER_H
+#define INPC_RASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define INPC_OK 0
+#define INPC_EINVAL (-1)       /* null pointer, negative size, bad enum */
+#define INPC_EWORKSPACE (-2)   /* a buffer is smaller than inpc_*_sizes() reports */
+#define INPC_EUNSUPPORTED (-3) /* F outside 1..64, image side outside 1..16383 */
+#define INPC_EOVERFLOW (-4)    /* too many points or pixels for the index widths */
+#define INPC_EHIP (-5)         /* a HIP runtime call failed; see inpc_last_hip_error() */
+
+typedef enum { INPC_F32 = 0, INPC_BF16 = 1 } inpc_dtype_t;
+
+/* What the forward keeps for the backward (Appendix A.6 stores the sorted
+ * key/index buffers; RECOMPUTE rebuilds them in the backward instead). */
+typedef enum { INPC_SAVE = 0, INPC_RECOMPUTE = 1 } inpc_bwd_mode_t;
+
+typedef struct {
+    float R[9];           /* world -> camera rotation, row-major */
+    float t[3];           /* world -> camera translation */
+    float fx, fy, cx, cy; /* pinhole intrinsics in pixels */
+    int32_t width, height;
+    float near_plane, far_plane; /* the paper uses 0.01 and 100 (Appendix A.2) */
+} inpc_camera_t;
+
+typedef struct {
+    float t_threshold; /* early-termination transmittance; 1e-4 in the paper; 0 disables */
+    int32_t mode;      /* inpc_bwd_mode_t */
+    int32_t tuning_id; /* -1: the autotuner's cached choice (else the default); >= 0: entry of the tuning table */
+    int32_t reserved;  /* must be 0 */
+} inpc_settings_t;
+
+/* One view of a batched call.  View v renders points
+ * [point_offset, point_offset + point_count) of the point arrays (views may
+ * share points) into pixels [pixel_offset, pixel_offset + W*H) of the packed
+ * image [sum_v W_v H_v, F]. */
+typedef struct {
+    inpc_camera_t cam;
+    int64_t point_offset;
+    int64_t point_count;
+    int64_t pixel_offset;
+} inpc_view_t;
+
+/* ---------------------------------------------------------------- sizes */
+
+/* Bytes needed by the plain (one-view) calls for N points and this camera.
+ * fwd_ws: forward workspace; saved: what the forward leaves for the backward
+ * (depends on mode); bwd_ws: backward workspace.  Any output may be NULL. */
+int inpc_plain_sizes(int64_t n_points, const inpc_camera_t *cam_host, int32_t F,
+                     int32_t feat_dtype, int32_t mode, size_t *fwd_ws, size_t *saved,
+                     size_t *bwd_ws);
+
+/* Same for a batched call over n_views views (host table). */
+int inpc_batched_sizes(const inpc_view_t *views_host, int32_t n_views, int64_t n_points,
+                       int32_t F, int32_t feat_dtype, int32_t mode, size_t *fwd_ws,
+                       size_t *saved, size_t *bwd_ws);
+
+/* ------------------------------------------------------------ plain calls */
+
+/* Forward rasterization of one view (Algorithm 1).
+ * xyz [N,3] f32, feat [N,F] (feat_dtype), opacity [N] f32 in [0,1];
+ * image [H,W,F] f32 and t_final [H,W] f32 are written in full.
+ * saved (saved_bytes) receives the state the backward needs; ws is scratch. */
+int inpc_rasterize_fwd(const float *xyz, const void *feat, int32_t feat_dtype,
+                       const float *opacity, int64_t n_points, int32_t F,
+                       const inpc_camera_t *cam_host, const inpc_settings_t *settings_host,
+                       float *image, float *t_final, void *saved, size_t saved_bytes, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Backward of inpc_rasterize_fwd for L with dL/dimage = grad_image [H,W,F]
+ * and dL/dt_final = grad_t_final [H,W] (may be NULL = zero).  The inputs and
+ * settings must be those of the forward that filled ``saved``.
+ * Writes grad_feat [N,F] f32 and grad_opacity [N] f32 in full (points that
+ * produce no blended splat get exact zeros).  Deterministic: no float
+ * atomics; every gradient is summed in a fixed order. */
+int inpc_rasterize_bwd(const float *xyz, const void *feat, int32_t feat_dtype,
+                       const float *opacity, int64_t n_points, int32_t F,
+                       const inpc_camera_t *cam_host, const inpc_settings_t *settings_host,
+                       const void *saved, size_t saved_bytes, const float *grad_image,
+                       const float *grad_t_final, float *grad_feat, float *grad_opacity,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------- batched calls */
+
+/* Forward over several views of uneven size and point count in one launch
+ * sequence: one projection, one global depth sort, one fragment emission,
+ * one global pixel sort and one blend for all views.  Packed outputs:
+ * image [sum P_v, F], t_final [sum P_v].  n_points is the length of the
+ * point arrays.  The view table is read on the host and passed to the
+ * kernels by value, so the call can be graph-captured. */
+int inpc_rasterize_fwd_batched(const float *xyz, const void *feat, int32_t feat_dtype,
+                               const float *opacity, int64_t n_points, int32_t F,
+                               const inpc_view_t *views_host, int32_t n_views,
+                               const inpc_settings_t *settings_host, float *image,
+                               float *t_final, void *saved, size_t saved_bytes, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* Backward of the batched forward.  Gradients are per *view point*: row
+ * (sum_{u<v} point_count_u) + i belongs to point point_offset_v + i of view
+ * v, so grad_feat is [sum_v point_count_v, F] and grad_opacity
+ * [sum_v point_count_v].  inpc_sum_view_grads() folds them onto the points. */
+int inpc_rasterize_bwd_batched(const float *xyz, const void *feat, int32_t feat_dtype,
+                               const float *opacity, int64_t n_points, int32_t F,
+                               const inpc_view_t *views_host, int32_t n_views,
+                               const inpc_settings_t *settings_host, const void *saved,
+                               size_t saved_bytes, const float *grad_image,
+                               const float *grad_t_final, float *grad_feat,
+                               float *grad_opacity, void *ws, size_t ws_bytes, void *stream);
+
+/* grad_feat[p] = sum over views v containing p, in view order, of the view
+ * point rows of p (and likewise grad_opacity).  Points no view contains get
+ * zeros.  Deterministic.  ws: at least 128 * n_views bytes of device scratch. */
+int inpc_sum_view_grads(const inpc_view_t *views_host, int32_t n_views, int64_t n_points,
+                        int32_t F, const float *view_grad_feat, const float *view_grad_opacity,
+                        float *grad_feat, float *grad_opacity, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* ----------------------------------------------------------- autotuning */
+
+/* Number of entries of the tuning table and a printable description. */
+int inpc_tuning_count(void);
+const char *inpc_tuning_name(int32_t tuning_id);
+
+/* Time every tuning-table entry on the given batched problem (forward and,
+ * if grad_image != NULL, backward; inputs as for the batched calls, with the
+ * workspace sized for the largest entry by inpc_batched_sizes) and record the
+ * fastest for its shape bucket.  Synchronises ``stream``.  If cache_path is
+ * not NULL the table of choices is merged into that JSON file.  Returns the
+ * chosen tuning id (>= 0) or a negative error code; *best_ms receives its
+ * time per call. */
+int inpc_autotune(const float *xyz, const void *feat, int32_t feat_dtype, const float *opacity,
+                  int64_t n_points, int32_t F, const inpc_view_t *views_host, int32_t n_views,
+                  float t_threshold, float *image, float *t_final, void *saved,
+                  size_t saved_bytes, const float *grad_image, float *grad_feat,
+                  float *grad_opacity, void *ws, size_t ws_bytes, int32_t repeats,
+                  const char *cache_path, float *best_ms, void *stream);
+
+/* Load choices written by inpc_autotune from a JSON file (merged into the
+ * in-process cache).  Returns the number of entries loaded or a negative code. */
+int inpc_autotune_load(const char *cache_path);
+
+/* Tuning id the library uses for this problem when settings.tuning_id == -1. */
+int inpc_tuning_for(const inpc_view_t *views_host, int32_t n_views, int64_t n_points, int32_t F,
+                    int32_t feat_dtype);
+
+/* ------------------------------------------------------ test/debug hooks */
+
+/* Copy the sorted fragment list of a SAVE-mode forward to the host
+ * (synchronises the stream).  saved and fwd_ws must be the buffers that
+ * forward used, untouched since.  keys_host[i] = (global pixel << 32) | float32
+ * bits of the view depth; ids_host[i] = 4*(view point) + corner, in sorted
+ * order; *m_out = number of fragments (arrays of capacity cap; nothing is
+ * copied if cap < *m_out).  n_blended_host (may be NULL) receives, per
+ * packed pixel, how many splats the blend consumed.  Not for the hot path:
+ * it allocates host staging memory. */
+int inpc_debug_fragments(const inpc_view_t *views_host, int32_t n_views, int64_t n_points,
+                         int32_t F, int32_t feat_dtype, const void *saved, size_t saved_bytes,
+                         const void *fwd_ws, size_t fwd_ws_bytes, uint64_t *keys_host,
+                         uint32_t *ids_host, int64_t cap, int64_t *m_out,
+                         uint32_t *n_blended_host, void *stream);
+
+const char *inpc_error_string(int code);
+const char *inpc_last_hip_error(void);
+int inpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INPC_RASTER_H */

@@ -1,0 +1,410 @@
+"""Python binding of the gfx950 bilinear point rasterizer (``libinpc_raster.so``).
+
+Argument marshalling only: every step of the forward and backward pass runs
+in the HIP kernels of the library (C ABI in ``include/inpc_raster.h``).
+PyTorch provides device memory, the current HIP stream and autograd.  If the
+library has not been built this module raises on first use; there is no
+fallback path.
+
+Entry points mirror the C ABI:
+
+* ``rasterize(xyz, feat, opa, cam, t_threshold=1e-4, mode="save")`` -- one
+  view, differentiable w.r.t. ``feat`` and ``opa`` (Algorithm 1 and the
+  backward of Appendix A.6);
+* ``rasterize_batched(xyz, feat, opa, views, ...)`` -- many views of uneven
+  size and point count in one launch sequence, packed outputs;
+* ``sum_view_grads`` -- fold per-view-point gradients onto shared points;
+* ``autotune`` / ``load_tuning`` -- the tuning-table search;
+* ``debug_fragments`` -- copy the sorted splat list of a forward to the host.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinpc_raster.so")
+
+INPC_F32, INPC_BF16 = 0, 1
+INPC_SAVE, INPC_RECOMPUTE = 0, 1
+ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EUNSUPPORTED", -4: "EOVERFLOW", -5: "EHIP"}
+
+
+class InpcError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what} failed: {ERRORS.get(code, code)}" + (f" ({detail})" if detail else ""))
+
+
+class CCamera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("near_plane", ctypes.c_float), ("far_plane", ctypes.c_float)]
+
+
+class CSettings(ctypes.Structure):
+    _fields_ = [("t_threshold", ctypes.c_float), ("mode", ctypes.c_int32),
+                ("tuning_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class CView(ctypes.Structure):
+    _fields_ = [("cam", CCamera), ("point_offset", ctypes.c_int64),
+                ("point_count", ctypes.c_int64), ("pixel_offset", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_16862_amd/build.py "
+                           "(or __graft_entry__.build()); there is no non-HIP fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    cam_p, set_p, view_p = ctypes.POINTER(CCamera), ctypes.POINTER(CSettings), ctypes.POINTER(CView)
+    sig = {
+        "inpc_plain_sizes": [i64, cam_p, i32, i32, i32, szp, szp, szp],
+        "inpc_batched_sizes": [view_p, i32, i64, i32, i32, i32, szp, szp, szp],
+        "inpc_rasterize_fwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, sz, P, sz, P],
+        "inpc_rasterize_bwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, sz, P, P, P, P, P, sz, P],
+        "inpc_rasterize_fwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, P, P, sz, P, sz, P],
+        "inpc_rasterize_bwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, sz, P, P, P, P, P,
+                                       sz, P],
+        "inpc_sum_view_grads": [view_p, i32, i64, i32, P, P, P, P, P, sz, P],
+        "inpc_tuning_count": [],
+        "inpc_tuning_name": [i32],
+        "inpc_autotune": [P, P, i32, P, i64, i32, view_p, i32, ctypes.c_float, P, P, P, sz, P, P, P, P, sz,
+                          i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), P],
+        "inpc_autotune_load": [ctypes.c_char_p],
+        "inpc_tuning_for": [view_p, i32, i64, i32, i32],
+        "inpc_debug_fragments": [view_p, i32, i64, i32, i32, P, sz, P, sz, P, P, i64,
+                                 ctypes.POINTER(ctypes.c_int64), P, P],
+        "inpc_error_string": [ctypes.c_int],
+        "inpc_last_hip_error": [],
+        "inpc_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.inpc_tuning_name.restype = ctypes.c_char_p
+    L.inpc_error_string.restype = ctypes.c_char_p
+    L.inpc_last_hip_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        detail = lib().inpc_last_hip_error().decode() if rc == -5 else ""
+        raise InpcError(rc, what, detail)
+    return rc
+
+
+# ------------------------------------------------------------------ marshalling
+def c_camera(cam) -> CCamera:
+    """From an object with R, t, fx, fy, cx, cy, width, height, near, far (or a dict)."""
+    d = cam.as_dict() if hasattr(cam, "as_dict") else dict(cam)
+    c = CCamera()
+    R = [float(x) for x in (d["R"].reshape(-1) if hasattr(d["R"], "reshape") else d["R"])]
+    t = [float(x) for x in (d["t"].reshape(-1) if hasattr(d["t"], "reshape") else d["t"])]
+    for i in range(9):
+        c.R[i] = R[i]
+    for i in range(3):
+        c.t[i] = t[i]
+    c.fx, c.fy, c.cx, c.cy = d["fx"], d["fy"], d["cx"], d["cy"]
+    c.width, c.height = int(d["width"]), int(d["height"])
+    c.near_plane = d.get("near", d.get("near_plane", 0.01))
+    c.far_plane = d.get("far", d.get("far_plane", 100.0))
+    return c
+
+
+def c_views(cams: Sequence, point_offsets: Sequence[int], point_counts: Sequence[int]):
+    arr = (CView * len(cams))()
+    pix = 0
+    for i, cam in enumerate(cams):
+        arr[i].cam = c_camera(cam)
+        arr[i].point_offset = int(point_offsets[i])
+        arr[i].point_count = int(point_counts[i])
+        arr[i].pixel_offset = pix
+        pix += arr[i].cam.width * arr[i].cam.height
+    return arr, pix
+
+
+def c_settings(t_threshold: float, mode: int, tuning_id: int) -> CSettings:
+    s = CSettings()
+    s.t_threshold = float(t_threshold)
+    s.mode = int(mode)
+    s.tuning_id = int(tuning_id)
+    s.reserved = 0
+    return s
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return {"save": INPC_SAVE, "recompute": INPC_RECOMPUTE}[mode]
+    return int(mode)
+
+
+def _fdt(feat: torch.Tensor) -> int:
+    if feat.dtype == torch.float32:
+        return INPC_F32
+    if feat.dtype == torch.bfloat16:
+        return INPC_BF16
+    raise TypeError(f"features must be float32 or bfloat16, got {feat.dtype}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _buffer(nbytes: int, device) -> torch.Tensor:
+    """Device byte buffer whose data pointer is 256-byte aligned."""
+    t = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t[off:off + max(int(nbytes), 1)]
+
+
+def _check_points(xyz: torch.Tensor, feat: torch.Tensor, opa: torch.Tensor):
+    if not (xyz.is_cuda and feat.is_cuda and opa.is_cuda):
+        raise ValueError("xyz, feat and opa must be device tensors")
+    if xyz.dtype != torch.float32 or opa.dtype != torch.float32:
+        raise TypeError("xyz and opacity must be float32")
+    if xyz.dim() != 2 or xyz.shape[1] != 3 or feat.dim() != 2 or opa.dim() != 1:
+        raise ValueError("expected xyz [N,3], feat [N,F], opa [N]")
+    if not (xyz.shape[0] == feat.shape[0] == opa.shape[0]):
+        raise ValueError("xyz, feat and opa disagree on N")
+
+
+# ------------------------------------------------------------------ plain calls
+def plain_sizes(n: int, cam, F: int, fdt: int, mode: int):
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    cc = c_camera(cam)
+    _check(lib().inpc_plain_sizes(int(n), ctypes.byref(cc), int(F), int(fdt), int(mode),
+                                  ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "inpc_plain_sizes")
+    return a.value, b.value, c.value
+
+
+def batched_sizes(views, n_views: int, n_points: int, F: int, fdt: int, mode: int):
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().inpc_batched_sizes(views, int(n_views), int(n_points), int(F), int(fdt), int(mode),
+                                    ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "inpc_batched_sizes")
+    return a.value, b.value, c.value
+
+
+@dataclass
+class ForwardState:
+    """What a forward leaves for its backward (and for debug_fragments)."""
+
+    saved: torch.Tensor
+    fwd_ws: Optional[torch.Tensor]
+    settings: CSettings
+    views: object
+    n_views: int
+    n_points: int
+    F: int
+    fdt: int
+
+
+def rasterize_forward(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save",
+                      tuning_id: int = -1, keep_workspace: bool = False):
+    """Forward only; returns (image [H,W,F], t_final [H,W], ForwardState)."""
+    _check_points(xyz, feat, opa)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    cams = [cam]
+    views, P = c_views(cams, [0], [xyz.shape[0]])
+    return _forward(xyz, feat, opa, views, 1, t_threshold, mode, tuning_id, keep_workspace,
+                    (views[0].cam.height, views[0].cam.width))
+
+
+def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_workspace, img_hw):
+    m = _mode(mode)
+    fdt = _fdt(feat)
+    F = int(feat.shape[1])
+    N = int(xyz.shape[0])
+    fws, sv, _ = batched_sizes(views, n_views, N, F, fdt, m)
+    dev = xyz.device
+    saved = _buffer(sv, dev)
+    ws = _buffer(fws, dev)
+    P = sum(views[i].cam.width * views[i].cam.height for i in range(n_views))
+    if img_hw is not None:
+        image = torch.empty((img_hw[0], img_hw[1], F), dtype=torch.float32, device=dev)
+        t_final = torch.empty(img_hw, dtype=torch.float32, device=dev)
+    else:
+        image = torch.empty((P, F), dtype=torch.float32, device=dev)
+        t_final = torch.empty((P,), dtype=torch.float32, device=dev)
+    st = c_settings(t_threshold, m, tuning_id)
+    _check(lib().inpc_rasterize_fwd_batched(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, views, n_views,
+                                            ctypes.byref(st), _ptr(image), _ptr(t_final), _ptr(saved),
+                                            saved.numel(), _ptr(ws), ws.numel(), _stream()),
+           "inpc_rasterize_fwd")
+    state = ForwardState(saved, ws if keep_workspace else None, st, views, n_views, N, F, fdt)
+    return image, t_final, state
+
+
+def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None):
+    """Backward of a forward; returns float32 (grad_feat, grad_opa) per view point."""
+    g_img = g_img.contiguous().float()
+    g_t = None if g_t is None else g_t.contiguous().float()
+    nvp = sum(int(state.views[i].point_count) for i in range(state.n_views))
+    _, _, bws = batched_sizes(state.views, state.n_views, state.n_points, state.F, state.fdt,
+                              state.settings.mode)
+    dev = xyz.device
+    ws = _buffer(bws, dev)
+    gf = torch.empty((nvp, state.F), dtype=torch.float32, device=dev)
+    go = torch.empty((nvp,), dtype=torch.float32, device=dev)
+    _check(lib().inpc_rasterize_bwd_batched(_ptr(xyz), _ptr(feat), state.fdt, _ptr(opa), state.n_points,
+                                            state.F, state.views, state.n_views,
+                                            ctypes.byref(state.settings), _ptr(state.saved),
+                                            state.saved.numel(), _ptr(g_img), _ptr(g_t), _ptr(gf),
+                                            _ptr(go), _ptr(ws), ws.numel(), _stream()),
+           "inpc_rasterize_bwd")
+    return gf, go
+
+
+class _Rasterize(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xyz, feat, opa, views, n_views, img_hw, t_threshold, mode, tuning_id, fold):
+        image, t_final, state = _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id,
+                                         False, img_hw)
+        ctx.state = state
+        ctx.fold = fold
+        ctx.save_for_backward(xyz, feat, opa)
+        return image, t_final
+
+    @staticmethod
+    def backward(ctx, g_img, g_t):
+        xyz, feat, opa = ctx.saved_tensors
+        st = ctx.state
+        if g_img is None:
+            P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
+            g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
+        gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
+        if ctx.fold:
+            gf, go = sum_view_grads(st.views, st.n_views, st.n_points, gf, go)
+        return None, gf, go, None, None, None, None, None, None, None
+
+
+def rasterize(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1):
+    """Differentiable rasterization of one view -> (image [H,W,F], t_final [H,W])."""
+    _check_points(xyz, feat, opa)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    views, _ = c_views([cam], [0], [xyz.shape[0]])
+    hw = (views[0].cam.height, views[0].cam.width)
+    return _Rasterize.apply(xyz, feat, opa, views, 1, hw, t_threshold, mode, tuning_id, False)
+
+
+def make_views(cams: Sequence, point_offsets: Sequence[int], point_counts: Sequence[int]):
+    """C view table for the batched calls (views packed in order)."""
+    views, _ = c_views(cams, point_offsets, point_counts)
+    return views
+
+
+def _is_identity_layout(views, n_views, n_points) -> bool:
+    off = 0
+    for i in range(n_views):
+        if views[i].point_offset != off:
+            return False
+        off += views[i].point_count
+    return off == n_points
+
+
+def rasterize_batched(xyz, feat, opa, views, t_threshold: float = 1e-4, mode="save",
+                      tuning_id: int = -1):
+    """Differentiable batched rasterization -> packed (image [sum P,F], t_final [sum P]).
+
+    ``views`` comes from ``make_views``.  Gradients w.r.t. feat/opa are folded
+    onto the points (views sharing points are summed in view order)."""
+    _check_points(xyz, feat, opa)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    n_views = len(views)
+    fold = not _is_identity_layout(views, n_views, xyz.shape[0])
+    return _Rasterize.apply(xyz, feat, opa, views, n_views, None, t_threshold, mode, tuning_id, fold)
+
+
+def sum_view_grads(views, n_views: int, n_points: int, vg_feat, vg_opa):
+    F = int(vg_feat.shape[1])
+    dev = vg_feat.device
+    gf = torch.empty((n_points, F), dtype=torch.float32, device=dev)
+    go = torch.empty((n_points,), dtype=torch.float32, device=dev)
+    ws = _buffer(128 * n_views, dev)
+    _check(lib().inpc_sum_view_grads(views, n_views, int(n_points), F, _ptr(vg_feat.contiguous()),
+                                     _ptr(vg_opa.contiguous()), _ptr(gf), _ptr(go), _ptr(ws), ws.numel(),
+                                     _stream()), "inpc_sum_view_grads")
+    return gf, go
+
+
+# ---------------------------------------------------------------- tuning, debug
+def tuning_table() -> List[str]:
+    L = lib()
+    return [L.inpc_tuning_name(i).decode() for i in range(L.inpc_tuning_count())]
+
+
+def load_tuning(path: str) -> int:
+    return _check(lib().inpc_autotune_load(path.encode()), "inpc_autotune_load")
+
+
+def autotune(xyz, feat, opa, views, t_threshold: float = 1e-4, g_img=None, repeats: int = 3,
+             cache_path: Optional[str] = None):
+    """Time every tuning-table entry on this problem; returns (best id, ms per call)."""
+    n_views = len(views)
+    N, F, fdt = int(xyz.shape[0]), int(feat.shape[1]), _fdt(feat)
+    fws, sv, bws = batched_sizes(views, n_views, N, F, fdt, INPC_SAVE)
+    dev = xyz.device
+    saved = _buffer(sv, dev)
+    ws = _buffer(max(fws, bws), dev)
+    P = sum(views[i].cam.width * views[i].cam.height for i in range(n_views))
+    nvp = sum(int(views[i].point_count) for i in range(n_views))
+    image = torch.empty((P, F), dtype=torch.float32, device=dev)
+    t_final = torch.empty((P,), dtype=torch.float32, device=dev)
+    gf = torch.empty((nvp, F), dtype=torch.float32, device=dev)
+    go = torch.empty((nvp,), dtype=torch.float32, device=dev)
+    ms = ctypes.c_float()
+    g = None if g_img is None else g_img.contiguous().float()
+    best = _check(lib().inpc_autotune(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, views, n_views,
+                                      float(t_threshold), _ptr(image), _ptr(t_final), _ptr(saved),
+                                      saved.numel(), _ptr(g), _ptr(gf), _ptr(go), _ptr(ws), ws.numel(),
+                                      int(repeats), cache_path.encode() if cache_path else None,
+                                      ctypes.byref(ms), _stream()), "inpc_autotune")
+    return best, ms.value
+
+
+def debug_fragments(state: ForwardState):
+    """Sorted (keys uint64, ids uint32) and n_blended per pixel of a SAVE-mode forward
+    made with keep_workspace=True."""
+    import numpy as np
+    if state.fwd_ws is None:
+        raise ValueError("forward must be called with keep_workspace=True")
+    m = ctypes.c_int64()
+    P = sum(state.views[i].cam.width * state.views[i].cam.height for i in range(state.n_views))
+    nb = np.empty(P, np.uint32)
+    L = lib()
+    _check(L.inpc_debug_fragments(state.views, state.n_views, state.n_points, state.F, state.fdt,
+                                  _ptr(state.saved), state.saved.numel(), _ptr(state.fwd_ws),
+                                  state.fwd_ws.numel(), None, None, 0, ctypes.byref(m),
+                                  nb.ctypes.data_as(ctypes.c_void_p), _stream()), "inpc_debug_fragments")
+    keys = np.empty(m.value, np.uint64)
+    ids = np.empty(m.value, np.uint32)
+    _check(L.inpc_debug_fragments(state.views, state.n_views, state.n_points, state.F, state.fdt,
+                                  _ptr(state.saved), state.saved.numel(), _ptr(state.fwd_ws),
+                                  state.fwd_ws.numel(), keys.ctypes.data_as(ctypes.c_void_p),
+                                  ids.ctypes.data_as(ctypes.c_void_p), m.value, ctypes.byref(m), None,
+                                  _stream()), "inpc_debug_fragments")
+    return keys, ids, nb

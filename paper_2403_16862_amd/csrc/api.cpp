@@ -1,0 +1,703 @@
+// C ABI of the rasterizer: argument validation, buffer layout and the launch
+// sequences of the forward (Algorithm 1) and backward (Appendix A.6) passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/inpc_raster.h"
+#include "internal.h"
+
+namespace inpc {
+
+// ------------------------------------------------------------ tuning table
+static const Tuning kTunings[] = {
+    {8, 8, 16, 8, "zsort 8-bit digits, pixel sort 8-bit digits, 4096-key tiles, 8x8 wave tiles"},
+    {11, 11, 16, 8, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
+    {8, 11, 16, 8, "zsort 8-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
+    {11, 11, 8, 8, "zsort 11-bit, pixel sort 11-bit, 2048-key tiles, 8x8 wave tiles"},
+    {11, 11, 16, 16, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 16x4 wave tiles"},
+    {11, 11, 16, 4, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 4x16 wave tiles"},
+    {10, 11, 16, 8, "zsort 10-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
+    {8, 8, 8, 8, "zsort 8-bit, pixel sort 8-bit, 2048-key tiles, 8x8 wave tiles"},
+};
+constexpr int kNumTunings = (int)(sizeof(kTunings) / sizeof(kTunings[0]));
+constexpr int kDefaultTuning = 0;
+
+int tuning_count() { return kNumTunings; }
+const Tuning& tuning(int id) { return kTunings[id]; }
+
+// --------------------------------------------------------------- errors
+static thread_local char g_hip_msg[256] = "";
+
+static int hip_fail(hipError_t e, const char* what) {
+    std::snprintf(g_hip_msg, sizeof g_hip_msg, "%s: %s", what, hipGetErrorString(e));
+    return INPC_EHIP;
+}
+
+static int check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return INPC_OK;
+}
+
+// ------------------------------------------------------------- problem
+struct Problem {
+    std::vector<GpuView> views;
+    int64_t n_points = 0;   // length of the point arrays
+    int64_t n_vp = 0;       // view points (sum of point counts)
+    int64_t n_pixels = 0;   // packed pixels
+    int64_t n_tiles = 0;    // blend tiles
+    int F = 0, fdt = 0, mode = 0;
+    int pixel_bits = 0;
+};
+
+static bool finite_f(float x) { return std::isfinite(x); }
+
+static int check_camera(const inpc_camera_t& c) {
+    if (c.width < 1 || c.height < 1) return INPC_EINVAL;
+    if (c.width > 16383 || c.height > 16383) return INPC_EUNSUPPORTED;
+    for (float x : c.R) if (!finite_f(x)) return INPC_EINVAL;
+    for (float x : c.t) if (!finite_f(x)) return INPC_EINVAL;
+    if (!finite_f(c.fx) || !finite_f(c.fy) || !finite_f(c.cx) || !finite_f(c.cy)) return INPC_EINVAL;
+    if (!(c.near_plane >= 0.0f) || !(c.far_plane > c.near_plane) || std::isnan(c.far_plane))
+        return INPC_EINVAL;
+    return INPC_OK;
+}
+
+// Builds the problem description from a host view table; wave_x of the
+// blend decides the tile grid, so it is part of the problem.
+static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points, int F, int fdt,
+                        int mode, int wave_x, Problem& pb) {
+    if (!views || n_views < 1 || n_points < 0) return INPC_EINVAL;
+    if (n_views > 65536) return INPC_EUNSUPPORTED;
+    if (F < 1 || F > 64) return INPC_EUNSUPPORTED;
+    if (fdt != INPC_F32 && fdt != INPC_BF16) return INPC_EINVAL;
+    if (mode != INPC_SAVE && mode != INPC_RECOMPUTE) return INPC_EINVAL;
+    pb = Problem{};
+    pb.n_points = n_points;
+    pb.F = F;
+    pb.fdt = fdt;
+    pb.mode = mode;
+    const int bw = blend_block_w(wave_x), bh = blend_block_h(wave_x);
+    int64_t vp = 0, pix = 0, tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const inpc_view_t& in = views[v];
+        const int rc = check_camera(in.cam);
+        if (rc) return rc;
+        if (in.point_offset < 0 || in.point_count < 0 || in.point_offset > n_points ||
+            in.point_count > n_points - in.point_offset)
+            return INPC_EINVAL;
+        if (in.pixel_offset != pix) return INPC_EINVAL;   // views are packed in order
+        GpuView g{};
+        std::memcpy(g.R, in.cam.R, sizeof g.R);
+        std::memcpy(g.t, in.cam.t, sizeof g.t);
+        g.fx = in.cam.fx; g.fy = in.cam.fy; g.cx = in.cam.cx; g.cy = in.cam.cy;
+        g.near_p = in.cam.near_plane; g.far_p = in.cam.far_plane;
+        g.W = in.cam.width; g.H = in.cam.height;
+        g.point_offset = in.point_offset;
+        g.vpoint_offset = vp;
+        g.point_count = in.point_count;
+        g.pixel_offset = pix;
+        g.tile_offset = tiles;
+        g.tiles_x = (g.W + bw - 1) / bw;
+        const int64_t tiles_y = (g.H + bh - 1) / bh;
+        pb.views.push_back(g);
+        vp += in.point_count;
+        pix += (int64_t)g.W * g.H;
+        tiles += g.tiles_x * tiles_y;
+        if (vp >= ((int64_t)1 << 28)) return INPC_EOVERFLOW;
+        if (pix >= (int64_t)0xFFFFFFFF) return INPC_EOVERFLOW;
+    }
+    if (tiles >= ((int64_t)1 << 31)) return INPC_EOVERFLOW;
+    pb.n_vp = vp;
+    pb.n_pixels = pix;
+    pb.n_tiles = tiles;
+    int bits = 0;
+    while (bits < 32 && (((int64_t)1 << bits) < pix)) ++bits;
+    pb.pixel_bits = bits;
+    return INPC_OK;
+}
+
+// ------------------------------------------------------------- layout
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+// Byte offsets of every buffer.  "fragment state" = point records, sorted
+// splat ids and per-pixel ranges; it lives in ``saved`` in SAVE mode and in
+// the workspace of whichever pass builds it in RECOMPUTE mode.
+struct FragOffsets {
+    size_t rec, ids, range;
+};
+struct BuildOffsets {  // transient buffers of the fragment build
+    size_t views, scalars, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, chunks, pk_a, pk_b, pv_other, counts;
+};
+struct Layout {
+    size_t saved_bytes, fwd_bytes, bwd_bytes;
+    size_t s_state, s_scalars;
+    FragOffsets saved_frag;     // valid in SAVE mode (offsets into saved)
+    FragOffsets fwd_frag;       // RECOMPUTE: offsets into fwd ws
+    FragOffsets bwd_frag;       // RECOMPUTE: offsets into bwd ws
+    BuildOffsets fwd_build, bwd_build;
+    size_t b_views, b_frec;
+};
+
+static size_t max_counts_words(const Problem& pb) {
+    size_t w = 0;
+    for (int i = 0; i < kNumTunings; ++i) {
+        const Tuning& t = kTunings[i];
+        w = std::max(w, sort_counts_words(t.zdigit, t.sort_items, pb.n_vp));
+        w = std::max(w, sort_counts_words(t.pdigit, t.sort_items, 4 * pb.n_vp));
+    }
+    return w;
+}
+
+static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
+    f.rec = c.take((size_t)pb.n_vp * sizeof(PointRec));
+    f.ids = c.take((size_t)4 * pb.n_vp * 4);
+    f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
+}
+
+static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
+    const size_t nv = (size_t)pb.n_vp, mb = 4 * nv;
+    b.views = c.take(pb.views.size() * sizeof(GpuView));
+    b.scalars = c.take(256);
+    b.zk_in = c.take(nv * 4);
+    b.zv_in = c.take(nv * 4);
+    b.zk_a = c.take(nv * 4);
+    b.zv_a = c.take(nv * 4);
+    b.zk_b = c.take(nv * 4);
+    b.zv_b = c.take(nv * 4);
+    b.chunks = c.take((emit_chunks(pb.n_vp) + 1) * 4);
+    b.pk_a = c.take(mb * 4);
+    b.pk_b = c.take(mb * 4);
+    b.pv_other = c.take(mb * 4);
+    b.counts = c.take(max_counts_words(pb) * 4);
+}
+
+static Layout make_layout(const Problem& pb) {
+    Layout L{};
+    Carver s, f, b;
+    L.s_state = s.take((size_t)pb.n_pixels * sizeof(PixelState));
+    L.s_scalars = s.take(256);
+    if (pb.mode == INPC_SAVE) carve_frag(s, pb, L.saved_frag);
+    carve_build(f, pb, L.fwd_build);
+    if (pb.mode == INPC_RECOMPUTE) carve_frag(f, pb, L.fwd_frag);
+    L.b_views = b.take(pb.views.size() * sizeof(GpuView));
+    L.b_frec = b.take((size_t)4 * pb.n_vp * sizeof(float2));
+    if (pb.mode == INPC_RECOMPUTE) {
+        carve_build(b, pb, L.bwd_build);
+        carve_frag(b, pb, L.bwd_frag);
+    }
+    L.saved_bytes = s.off;
+    L.fwd_bytes = f.off;
+    L.bwd_bytes = b.off;
+    return L;
+}
+
+template <typename T>
+static T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// ------------------------------------------------------------ autotuner
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+
+static std::string bucket_key(const Problem& pb) {
+    auto lg = [](int64_t x) {
+        int b = 0;
+        while (((int64_t)1 << b) < x) ++b;
+        return b;
+    };
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "gfx950|V%d|N%d|P%d|F%d|T%d", (int)pb.views.size(), lg(pb.n_vp),
+                  lg(pb.n_pixels), pb.F, pb.fdt);
+    return buf;
+}
+
+static int resolve_tuning(int requested, const Problem& pb) {
+    if (requested >= 0) return requested;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(bucket_key(pb));
+    return it == g_tune_cache.end() ? kDefaultTuning : it->second;
+}
+
+// ------------------------------------------------- the fragment build
+// Algorithm 1 up to the sorted, segmented splat list: projection and
+// culling, depth sort of the points, order-preserving splat emission, global
+// pixel sort, per-pixel ranges.  The depth digits of the (pixel, depth) key
+// are sorted on the points (all splats of a point share its depth), so the
+// splat-level sort only runs the pixel digits; together the passes form one
+// stable LSD radix sort of the 64-bit (pixel << 32 | depth) keys.
+static void build_fragments(const Problem& pb, const Tuning& tn, const float* xyz,
+                            const float* opacity, void* frag_base, const FragOffsets& fo,
+                            void* build_base, const BuildOffsets& bo, uint32_t* m_dev,
+                            hipStream_t s) {
+    GpuView* views = at<GpuView>(build_base, bo.views);
+    const int nv = (int)pb.views.size();
+    launch_upload_views(pb.views.data(), nv, views, s);
+    PointRec* rec = at<PointRec>(frag_base, fo.rec);
+    uint32_t* zk_in = at<uint32_t>(build_base, bo.zk_in);
+    uint32_t* zv_in = at<uint32_t>(build_base, bo.zv_in);
+    launch_project(xyz, opacity, views, nv, pb.n_vp, rec, zk_in, zv_in, s);
+    uint32_t* zk_a = at<uint32_t>(build_base, bo.zk_a);
+    uint32_t* zv_a = at<uint32_t>(build_base, bo.zv_a);
+    uint32_t* zk_b = at<uint32_t>(build_base, bo.zk_b);
+    uint32_t* zv_b = at<uint32_t>(build_base, bo.zv_b);
+    uint32_t* counts = at<uint32_t>(build_base, bo.counts);
+    launch_radix_sort(tn.zdigit, tn.sort_items, 32, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
+                      pb.n_vp, counts, s);
+    const int zp = radix_passes(tn.zdigit, 32);
+    const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
+
+    // Pixel sort: emission writes (kb, vb); the sorted ids must end in the
+    // fragment-state id buffer.
+    const int pp = radix_passes(tn.pdigit, pb.pixel_bits);
+    uint32_t* ids_final = at<uint32_t>(frag_base, fo.ids);
+    uint32_t* pv_other = at<uint32_t>(build_base, bo.pv_other);
+    uint32_t* pk_a = at<uint32_t>(build_base, bo.pk_a);
+    uint32_t* pk_b = at<uint32_t>(build_base, bo.pk_b);
+    uint32_t* pv_a = (pp & 1) ? ids_final : pv_other;
+    uint32_t* pv_b = (pp & 1) ? pv_other : ids_final;
+    launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
+                pv_b, s);
+    launch_radix_sort(tn.pdigit, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
+                      m_dev, 4 * pb.n_vp, counts, s);
+    const uint32_t* pk_sorted = (pp & 1) ? pk_a : pk_b;
+    launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, pb.n_pixels, at<uint2>(frag_base, fo.range), s);
+}
+
+// ------------------------------------------------------------- forward
+static int forward(const Problem& pb, int tid, const float* xyz, const void* feat,
+                   const float* opacity, float tau, float* image, float* t_final, void* saved,
+                   size_t saved_bytes, void* ws, size_t ws_bytes, hipStream_t s) {
+    const Layout L = make_layout(pb);
+    if (saved_bytes < L.saved_bytes || ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
+    if (pb.n_pixels > 0 && (!saved || !ws)) return INPC_EINVAL;
+    const Tuning& tn = kTunings[tid];
+    uint32_t* m_dev = at<uint32_t>(saved, L.s_scalars);
+    void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
+    const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
+    build_fragments(pb, tn, xyz, opacity, frag_base, fo, ws, L.fwd_build, m_dev, s);
+    launch_blend_fwd(pb.F, pb.fdt, tn.blend_wave_x, at<GpuView>(ws, L.fwd_build.views),
+                     (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
+                     at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
+                     image, t_final, at<PixelState>(saved, L.s_state), s);
+    return check_launch("inpc forward");
+}
+
+// ------------------------------------------------------------ backward
+static int backward(const Problem& pb, int tid, const float* xyz, const void* feat,
+                    const float* opacity, const void* saved, size_t saved_bytes,
+                    const float* g_img, const float* g_t, float* grad_feat, float* grad_opa,
+                    void* ws, size_t ws_bytes, hipStream_t s) {
+    const Layout L = make_layout(pb);
+    if (saved_bytes < L.saved_bytes || ws_bytes < L.bwd_bytes) return INPC_EWORKSPACE;
+    if (pb.n_vp > 0 && (!saved || !ws)) return INPC_EINVAL;
+    const Tuning& tn = kTunings[tid];
+    void* sv = const_cast<void*>(saved);
+    const void* frag_base;
+    const FragOffsets* fo;
+    const GpuView* views;
+    if (pb.mode == INPC_SAVE) {
+        launch_upload_views(pb.views.data(), (int)pb.views.size(), at<GpuView>(ws, L.b_views), s);
+        views = at<GpuView>(ws, L.b_views);
+        frag_base = saved;
+        fo = &L.saved_frag;
+    } else {
+        // Rebuild the fragment state exactly as the forward did.
+        build_fragments(pb, tn, xyz, opacity, ws, L.bwd_frag, ws, L.bwd_build,
+                        at<uint32_t>(ws, L.bwd_build.scalars), s);
+        views = at<GpuView>(ws, L.bwd_build.views);
+        frag_base = ws;
+        fo = &L.bwd_frag;
+    }
+    float2* frec = at<float2>(ws, L.b_frec);
+    launch_fill_u32(reinterpret_cast<uint32_t*>(frec), 0u, (size_t)8 * pb.n_vp, s);
+    launch_blend_bwd(pb.F, pb.fdt, tn.blend_wave_x, views, (int)pb.views.size(), pb.n_tiles,
+                     at<const uint2>(const_cast<void*>(frag_base), fo->range),
+                     at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
+                     at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat,
+                     at<const PixelState>(sv, L.s_state), g_img, g_t, frec, s);
+    launch_point_reduce(pb.F, views, (int)pb.views.size(), pb.n_vp,
+                        at<const PointRec>(const_cast<void*>(frag_base), fo->rec), frec, g_img,
+                        grad_feat, grad_opa, s);
+    return check_launch("inpc backward");
+}
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static int check_settings(const inpc_settings_t* st, int* tuning_req, float* tau, int* mode) {
+    if (!st) return INPC_EINVAL;
+    if (st->reserved != 0) return INPC_EINVAL;
+    if (!std::isfinite(st->t_threshold) || st->t_threshold < 0.0f) return INPC_EINVAL;
+    if (st->tuning_id < -1 || st->tuning_id >= kNumTunings) return INPC_EINVAL;
+    if (st->mode != INPC_SAVE && st->mode != INPC_RECOMPUTE) return INPC_EINVAL;
+    *tuning_req = st->tuning_id;
+    *tau = st->t_threshold;
+    *mode = st->mode;
+    return INPC_OK;
+}
+
+static int check_arrays(const Problem& pb, const float* xyz, const void* feat, const float* opa) {
+    if (pb.n_points > 0 && (!xyz || !feat || !opa)) return INPC_EINVAL;
+    if (pb.n_points > 0 && (!aligned(xyz, 4) || !aligned(opa, 4) || !aligned(feat, 16)))
+        return INPC_EINVAL;
+    return INPC_OK;
+}
+
+static inpc_view_t single_view(const inpc_camera_t* cam, int64_t n_points) {
+    inpc_view_t v{};
+    v.cam = *cam;
+    v.point_offset = 0;
+    v.point_count = n_points;
+    v.pixel_offset = 0;
+    return v;
+}
+
+static int wave_x_of(int tid) { return kTunings[tid].blend_wave_x; }
+
+// Problem for sizing: tile counts do not enter any buffer size.
+static int sizes_impl(const inpc_view_t* views, int n_views, int64_t n_points, int F, int fdt,
+                      int mode, size_t* fwd_ws, size_t* saved, size_t* bwd_ws) {
+    Problem pb;
+    const int rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    if (rc) return rc;
+    const Layout L = make_layout(pb);
+    if (fwd_ws) *fwd_ws = L.fwd_bytes;
+    if (saved) *saved = L.saved_bytes;
+    if (bwd_ws) *bwd_ws = L.bwd_bytes;
+    return INPC_OK;
+}
+
+static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                    float* image, float* t_final, void* saved, size_t saved_bytes, void* ws,
+                    size_t ws_bytes, void* stream) {
+    int treq, mode;
+    float tau;
+    int rc = check_settings(st, &treq, &tau, &mode);
+    if (rc) return rc;
+    Problem pb;
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    if (rc) return rc;
+    const int tid = resolve_tuning(treq, pb);
+    if (wave_x_of(tid) != 8) {
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, wave_x_of(tid), pb);
+        if (rc) return rc;
+    }
+    rc = check_arrays(pb, xyz, feat, opa);
+    if (rc) return rc;
+    if (!image || !t_final || !aligned(image, 16) || !aligned(t_final, 4)) return INPC_EINVAL;
+    if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
+    return forward(pb, tid, xyz, feat, opa, tau, image, t_final, saved, saved_bytes, ws, ws_bytes,
+                   static_cast<hipStream_t>(stream));
+}
+
+static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                    const void* saved, size_t saved_bytes, const float* g_img, const float* g_t,
+                    float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes, void* stream) {
+    int treq, mode;
+    float tau;
+    int rc = check_settings(st, &treq, &tau, &mode);
+    if (rc) return rc;
+    Problem pb;
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    if (rc) return rc;
+    const int tid = resolve_tuning(treq, pb);
+    if (wave_x_of(tid) != 8) {
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, wave_x_of(tid), pb);
+        if (rc) return rc;
+    }
+    rc = check_arrays(pb, xyz, feat, opa);
+    if (rc) return rc;
+    if (!g_img || !aligned(g_img, 16) || (g_t && !aligned(g_t, 4))) return INPC_EINVAL;
+    if (pb.n_vp > 0 && (!grad_feat || !grad_opa || !aligned(grad_feat, 16) || !aligned(grad_opa, 4)))
+        return INPC_EINVAL;
+    if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
+    return backward(pb, tid, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa, ws,
+                    ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+}  // namespace inpc
+
+using namespace inpc;
+
+extern "C" {
+
+int inpc_version(void) { return 1; }
+
+const char* inpc_error_string(int code) {
+    switch (code) {
+        case INPC_OK: return "ok";
+        case INPC_EINVAL: return "invalid argument";
+        case INPC_EWORKSPACE: return "workspace or saved buffer too small";
+        case INPC_EUNSUPPORTED: return "unsupported feature count or image size";
+        case INPC_EOVERFLOW: return "too many points or pixels for the index widths";
+        case INPC_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+const char* inpc_last_hip_error(void) { return g_hip_msg; }
+
+int inpc_plain_sizes(int64_t n_points, const inpc_camera_t* cam, int32_t F, int32_t fdt,
+                     int32_t mode, size_t* fwd_ws, size_t* saved, size_t* bwd_ws) {
+    if (!cam) return INPC_EINVAL;
+    const inpc_view_t v = single_view(cam, n_points);
+    return sizes_impl(&v, 1, n_points, F, fdt, mode, fwd_ws, saved, bwd_ws);
+}
+
+int inpc_batched_sizes(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
+                       int32_t fdt, int32_t mode, size_t* fwd_ws, size_t* saved, size_t* bwd_ws) {
+    return sizes_impl(views, n_views, n_points, F, fdt, mode, fwd_ws, saved, bwd_ws);
+}
+
+int inpc_rasterize_fwd(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                       int64_t n_points, int32_t F, const inpc_camera_t* cam,
+                       const inpc_settings_t* st, float* image, float* t_final, void* saved,
+                       size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return INPC_EINVAL;
+    const inpc_view_t v = single_view(cam, n_points);
+    return fwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, image, t_final, saved, saved_bytes,
+                    ws, ws_bytes, stream);
+}
+
+int inpc_rasterize_bwd(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                       int64_t n_points, int32_t F, const inpc_camera_t* cam,
+                       const inpc_settings_t* st, const void* saved, size_t saved_bytes,
+                       const float* g_img, const float* g_t, float* grad_feat, float* grad_opa,
+                       void* ws, size_t ws_bytes, void* stream) {
+    if (!cam) return INPC_EINVAL;
+    const inpc_view_t v = single_view(cam, n_points);
+    return bwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, saved, saved_bytes, g_img, g_t,
+                    grad_feat, grad_opa, ws, ws_bytes, stream);
+}
+
+int inpc_rasterize_fwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                               int64_t n_points, int32_t F, const inpc_view_t* views,
+                               int32_t n_views, const inpc_settings_t* st, float* image,
+                               float* t_final, void* saved, size_t saved_bytes, void* ws,
+                               size_t ws_bytes, void* stream) {
+    return fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, st, image, t_final, saved,
+                    saved_bytes, ws, ws_bytes, stream);
+}
+
+int inpc_rasterize_bwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                               int64_t n_points, int32_t F, const inpc_view_t* views,
+                               int32_t n_views, const inpc_settings_t* st, const void* saved,
+                               size_t saved_bytes, const float* g_img, const float* g_t,
+                               float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes,
+                               void* stream) {
+    return bwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, st, saved, saved_bytes, g_img,
+                    g_t, grad_feat, grad_opa, ws, ws_bytes, stream);
+}
+
+int inpc_sum_view_grads(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
+                        const float* vg_feat, const float* vg_opa, float* g_feat, float* g_opa,
+                        void* ws, size_t ws_bytes, void* stream) {
+    Problem pb;
+    int rc = make_problem(views, n_views, n_points, F, INPC_F32, INPC_SAVE, 8, pb);
+    if (rc) return rc;
+    if (n_points > 0 && (!g_feat || !g_opa || !aligned(g_feat, 16))) return INPC_EINVAL;
+    if (pb.n_vp > 0 && (!vg_feat || !vg_opa || !aligned(vg_feat, 16))) return INPC_EINVAL;
+    if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
+    if (ws_bytes < pb.views.size() * sizeof(GpuView)) return INPC_EWORKSPACE;
+    if (n_points == 0) return INPC_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GpuView* dv = static_cast<GpuView*>(ws);
+    launch_upload_views(pb.views.data(), (int)pb.views.size(), dv, s);
+    launch_sum_view_grads(dv, (int)pb.views.size(), n_points, F, vg_feat, vg_opa, g_feat, g_opa, s);
+    return check_launch("inpc_sum_view_grads");
+}
+
+int inpc_tuning_count(void) { return kNumTunings; }
+
+const char* inpc_tuning_name(int32_t id) {
+    if (id < 0 || id >= kNumTunings) return "";
+    return kTunings[id].name;
+}
+
+int inpc_tuning_for(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
+                    int32_t fdt) {
+    Problem pb;
+    const int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    if (rc) return rc;
+    return resolve_tuning(-1, pb);
+}
+
+
+int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
+                         int32_t fdt, const void* saved, size_t saved_bytes, const void* fwd_ws,
+                         size_t fwd_ws_bytes, uint64_t* keys_host, uint32_t* ids_host, int64_t cap,
+                         int64_t* m_out, uint32_t* n_blended_host, void* stream) {
+    Problem pb;
+    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    if (rc) return rc;
+    if (!saved || !fwd_ws || !m_out) return INPC_EINVAL;
+    const Layout L = make_layout(pb);
+    if (saved_bytes < L.saved_bytes || fwd_ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments sync");
+    uint32_t m = 0;
+    e = hipMemcpy(&m, at<const uint32_t>(const_cast<void*>(saved), L.s_scalars), 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
+    *m_out = m;
+    if (n_blended_host) {
+        std::vector<PixelState> st((size_t)pb.n_pixels);
+        e = hipMemcpy(st.data(), at<const PixelState>(const_cast<void*>(saved), L.s_state),
+                      st.size() * sizeof(PixelState), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
+        for (size_t q = 0; q < st.size(); ++q) n_blended_host[q] = st[q].n_blended;
+    }
+    if (!keys_host || !ids_host || cap < (int64_t)m) return INPC_OK;
+    std::vector<uint2> range((size_t)pb.n_pixels);
+    std::vector<uint32_t> zk((size_t)pb.n_vp);
+    if (m) {
+        e = hipMemcpy(ids_host, at<const uint32_t>(const_cast<void*>(saved), L.saved_frag.ids),
+                      (size_t)m * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
+    }
+    e = hipMemcpy(range.data(), at<const uint2>(const_cast<void*>(saved), L.saved_frag.range),
+                  range.size() * sizeof(uint2), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
+    if (!zk.empty()) {
+        e = hipMemcpy(zk.data(), at<const uint32_t>(const_cast<void*>(fwd_ws), L.fwd_build.zk_in),
+                      zk.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
+    }
+    // Keys from the device's own data: the pixel that owns each sorted slot
+    // (from the per-pixel ranges) and the depth bits of the slot's point.
+    for (int64_t q = 0; q < pb.n_pixels; ++q) {
+        for (uint32_t i = range[q].x; i < range[q].y && i < m; ++i) {
+            const uint32_t vp = ids_host[i] >> 2;
+            const uint32_t zb = vp < zk.size() ? zk[vp] : 0xFFFFFFFFu;
+            keys_host[i] = ((uint64_t)q << 32) | zb;
+        }
+    }
+    return INPC_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+static bool cache_merge_file(const char* path) {
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    size_t pos = 0;
+    int loaded = 0;
+    while ((pos = text.find('"', pos)) != std::string::npos) {
+        const size_t end = text.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = text.substr(pos + 1, end - pos - 1);
+        const size_t colon = text.find(':', end);
+        if (colon == std::string::npos) break;
+        int id = -1;
+        if (std::sscanf(text.c_str() + colon + 1, "%d", &id) == 1 && id >= 0 && id < kNumTunings &&
+            key.rfind("gfx950|", 0) == 0) {
+            g_tune_cache[key] = id;
+            ++loaded;
+        }
+        pos = colon + 1;
+    }
+    return loaded >= 0;
+}
+
+static bool cache_write_file(const char* path) {
+    std::FILE* f = std::fopen(path, "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : g_tune_cache)
+        std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < g_tune_cache.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    return true;
+}
+
+int inpc_autotune_load(const char* path) {
+    if (!path) return INPC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const size_t before = g_tune_cache.size();
+    if (!cache_merge_file(path)) return INPC_EINVAL;
+    return (int)(g_tune_cache.size() - before);
+}
+
+int inpc_autotune(const float* xyz, const void* feat, int32_t fdt, const float* opa, int64_t n_points,
+                  int32_t F, const inpc_view_t* views, int32_t n_views, float tau, float* image,
+                  float* t_final, void* saved, size_t saved_bytes, const float* g_img,
+                  float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes, int32_t repeats,
+                  const char* cache_path, float* best_ms, void* stream) {
+    if (repeats < 1) repeats = 1;
+    Problem pb;
+    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return hip_fail(hipGetLastError(), "inpc_autotune events");
+    int best = -1;
+    float best_t = 0.0f;
+    for (int tid = 0; tid < kNumTunings; ++tid) {
+        inpc_settings_t st{tau, INPC_SAVE, tid, 0};
+        auto step = [&]() -> int {
+            int r = fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, image, t_final, saved,
+                             saved_bytes, ws, ws_bytes, stream);
+            if (r || !g_img) return r;
+            return bwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, saved, saved_bytes,
+                            g_img, nullptr, grad_feat, grad_opa, ws, ws_bytes, stream);
+        };
+        rc = step();
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < repeats && rc == 0; ++r) rc = step();
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = hip_fail(hipGetLastError(), "inpc_autotune sync");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)repeats;
+        if (best < 0 || ms < best_t) {
+            best = tid;
+            best_t = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[bucket_key(pb)] = best;
+        if (cache_path) {
+            cache_merge_file(cache_path);
+            g_tune_cache[bucket_key(pb)] = best;
+            cache_write_file(cache_path);
+        }
+    }
+    if (best_ms) *best_ms = best_t;
+    return best;
+}
+
+}  // extern "C"

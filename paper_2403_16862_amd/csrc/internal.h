@@ -1,0 +1,90 @@
+// Host-side interface between the C ABI (api.cpp) and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace inpc {
+
+// One entry of the tuning table: radix digit widths of the two sorts, keys
+// per sort tile (BLOCK * items) and blend tile shape.
+struct Tuning {
+    int zdigit;       // digit bits of the per-point depth sort
+    int pdigit;       // digit bits of the per-fragment pixel sort
+    int sort_items;   // keys per thread in a sort tile (tile = 256 * items)
+    int blend_wave_x; // blend: pixels per wave along x (wave covers wave_x * (64/wave_x))
+    const char* name;
+};
+
+int tuning_count();
+const Tuning& tuning(int id);
+
+// ------------------------------------------------------------------ launchers
+void launch_upload_views(const GpuView* host_views, int n, GpuView* dev, hipStream_t s);
+
+void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+
+void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
+                    int64_t n_vp, PointRec* rec, uint32_t* zkey, uint32_t* zval, hipStream_t s);
+
+// Emission of the fragments of depth-sorted view points (count, scan, write).
+constexpr int kEmitBlock = 256;
+constexpr int kEmitItems = 4;
+size_t emit_chunks(int64_t n_vp);
+void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+                 int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev,
+                 uint32_t* pkey, uint32_t* pid, hipStream_t s);
+
+// Stable LSD radix sort of (u32 key, u32 value) pairs over key bits
+// [0, bits).  n_dev (may be null) holds the live element count on the
+// device; n_bound bounds it and sizes the grid.  Pass 0 reads (kin, vin) and
+// writes (ka, va); later passes alternate between (ka, va) and (kb, vb), so
+// the result is in (ka, va) after an odd number of passes (radix_passes)
+// and in (kb, vb) after an even number (in (kin, vin) after none).
+// (kin, vin) may alias (kb, vb).  counts holds sort_counts_words() words.
+size_t sort_counts_words(int digit, int items, int64_t n_bound);
+void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
+                       uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s);
+int radix_passes(int digit, int bits);
+bool sort_valid(int digit, int items);
+
+// Per-pixel [start, end) ranges of the pixel-sorted fragment keys.
+void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
+                   int64_t n_pixels, uint2* range, hipStream_t s);
+
+// Per-pixel state kept from the forward blend for the backward.
+struct alignas(16) PixelState {
+    uint32_t n_blended;  // splats blended before termination
+    uint32_t j_last;     // last blended index k with T_k > 0 (valid if n_blended > 0)
+    float t_last;        // T_{j_last}
+    uint32_t pad;
+};
+
+void launch_blend_fwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
+                      int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
+                      const void* feat, float tau, float* image, float* t_final, PixelState* state,
+                      hipStream_t s);
+
+void launch_blend_bwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
+                      int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
+                      const void* feat, const PixelState* state, const float* g_img,
+                      const float* g_t, float2* frec, hipStream_t s);
+
+void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
+                         const PointRec* rec, const float2* frec, const float* g_img,
+                         float* grad_feat, float* grad_opa, hipStream_t s);
+
+void launch_sum_view_grads(const GpuView* views, int n_views, int64_t n_points, int F,
+                           const float* vg_feat, const float* vg_opa, float* g_feat, float* g_opa,
+                           hipStream_t s);
+
+// Tile geometry of the blend: a block of 4 waves covers a 2x2 arrangement of
+// wave tiles; a wave tile is wave_x pixels wide and 64/wave_x tall.
+inline int blend_block_w(int wave_x) { return 2 * wave_x; }
+inline int blend_block_h(int wave_x) { return 2 * (64 / wave_x); }
+
+}  // namespace inpc

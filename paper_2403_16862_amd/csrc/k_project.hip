@@ -1,0 +1,221 @@
+// Projection / culling (Section 3.4, Eq. 5) and bilinear splat emission
+// (Section 3.4, Eq. 6; the BilinearSplatting and ExclusiveSum steps of
+// Algorithm 1) for gfx950.
+#include "internal.h"
+
+namespace inpc {
+
+// ------------------------------------------------------------- view upload
+constexpr int kUploadChunk = 16;
+struct ViewChunk {
+    GpuView v[kUploadChunk];
+};
+
+__global__ void k_upload_views(ViewChunk chunk, int n, GpuView* __restrict__ dst) {
+    // One thread per 16-byte word of the chunk.
+    const int words = n * (int)(sizeof(GpuView) / 16);
+    const int i = threadIdx.x;
+    if (i < words) reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(chunk.v)[i];
+}
+
+void launch_upload_views(const GpuView* host_views, int n, GpuView* dev, hipStream_t s) {
+    for (int base = 0; base < n; base += kUploadChunk) {
+        ViewChunk c{};
+        const int k = (n - base) < kUploadChunk ? (n - base) : kUploadChunk;
+        for (int i = 0; i < k; ++i) c.v[i] = host_views[base + i];
+        hipLaunchKernelGGL(k_upload_views, dim3(1), dim3(kUploadChunk * sizeof(GpuView) / 16), 0, s,
+                           c, k, dev + base);
+    }
+}
+
+// --------------------------------------------------------------------- fill
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x * 4;
+    for (size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < n; i += stride) {
+        if (i + 4 <= n) {
+            reinterpret_cast<uint4*>(p + i)[0] = make_uint4(value, value, value, value);
+        } else {
+            for (size_t j = i; j < n; ++j) p[j] = value;
+        }
+    }
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    size_t blocks = (n / 4 + 255) / 256 + 1;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, n);
+}
+
+// --------------------------------------------------------------- projection
+// The float32 operations below decide which splats exist and where, so they
+// are evaluated exactly as written: no contraction into fused multiply-adds,
+// correctly rounded division, and this association order.
+__device__ __forceinline__ void project_point(const GpuView& V, float x, float y, float z,
+                                              PointRec& r, uint32_t& zbits) {
+#pragma clang fp contract(off)
+    const float xc = ((V.R[0] * x + V.R[1] * y) + V.R[2] * z) + V.t[0];
+    const float yc = ((V.R[3] * x + V.R[4] * y) + V.R[5] * z) + V.t[1];
+    const float zc = ((V.R[6] * x + V.R[7] * y) + V.R[8] * z) + V.t[2];
+    r.ax = 0.0f;
+    r.ay = 0.0f;
+    r.anc = 0u;
+    zbits = kCulledKey;
+    if (!(zc > V.near_p && zc < V.far_p)) return;
+    const float u = V.fx * (xc / zc) + V.cx;
+    const float v = V.fy * (yc / zc) + V.cy;
+    if (!(u > -1.0f && u < (float)(V.W + 1))) return;
+    if (!(v > -1.0f && v < (float)(V.H + 1))) return;
+    const float su = u - 0.5f, sv = v - 0.5f;
+    const float fx0 = floorf(su), fy0 = floorf(sv);
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const float ax = su - (float)x0, ay = sv - (float)y0;
+    const float wx0 = 1.0f - ax, wy0 = 1.0f - ay;
+    uint32_t mask = 0;
+    const bool col0 = x0 >= 0 && x0 < V.W && wx0 > 0.0f;
+    const bool col1 = x0 + 1 >= 0 && x0 + 1 < V.W && ax > 0.0f;
+    const bool row0 = y0 >= 0 && y0 < V.H && wy0 > 0.0f;
+    const bool row1 = y0 + 1 >= 0 && y0 + 1 < V.H && ay > 0.0f;
+    mask |= (col0 && row0) ? 1u : 0u;
+    mask |= (col1 && row0) ? 2u : 0u;
+    mask |= (col0 && row1) ? 4u : 0u;
+    mask |= (col1 && row1) ? 8u : 0u;
+    if (mask == 0u) return;
+    r.ax = ax;
+    r.ay = ay;
+    r.anc = (uint32_t)(x0 + 1) | ((uint32_t)(y0 + 1) << 14) | (mask << 28);
+    zbits = __float_as_uint(zc);
+}
+
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
+                                                 const float* __restrict__ opacity,
+                                                 const GpuView* __restrict__ views, int n_views,
+                                                 int64_t n_vp, PointRec* __restrict__ rec,
+                                                 uint32_t* __restrict__ zkey,
+                                                 uint32_t* __restrict__ zval) {
+    const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vp >= n_vp) return;
+    const int v = n_views == 1 ? 0
+                               : find_view(views, n_views, vp,
+                                           [](const GpuView& g) { return g.vpoint_offset; });
+    const GpuView& V = views[v];
+    const int64_t p = V.point_offset + (vp - V.vpoint_offset);
+    const float x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
+    PointRec r;
+    uint32_t zb;
+    project_point(V, x, y, z, r, zb);
+    r.opa = opacity[p];
+    rec[vp] = r;
+    zkey[vp] = zb;
+    zval[vp] = (uint32_t)vp | (anc_mask(r.anc) << 28);
+}
+
+void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
+                    int64_t n_vp, PointRec* rec, uint32_t* zkey, uint32_t* zval, hipStream_t s) {
+    if (n_vp == 0) return;
+    const int64_t blocks = (n_vp + 255) / 256;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, xyz, opa, views, n_views,
+                       n_vp, rec, zkey, zval);
+}
+
+// ----------------------------------------------------------------- emission
+// Fragments are emitted in the order of the depth-sorted points, corners in
+// ascending order, so the emitted sequence is ordered by (depth, splat id).
+// Count -> exclusive scan of chunk counts -> order-preserving write.
+constexpr int kChunk = kEmitBlock * kEmitItems;
+
+size_t emit_chunks(int64_t n_vp) { return (size_t)((n_vp + kChunk - 1) / kChunk); }
+
+__global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __restrict__ zval,
+                                                           int64_t n_vp,
+                                                           uint32_t* __restrict__ chunk_cnt) {
+    __shared__ uint32_t s_tmp[kEmitBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i)
+        if (base + i < n_vp) cnt += __popc(zval[base + i] >> 28);
+    uint32_t total;
+    block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
+    if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
+}
+
+// Exclusive scan of the chunk counts in one block; writes the total (the
+// fragment count M) to m_dev.
+__global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt, size_t n,
+                                                      uint32_t* __restrict__ m_dev) {
+    __shared__ uint32_t s_tmp[1024 / kWave];
+    uint32_t running = 0;
+    for (size_t base = 0; base < n; base += 1024) {
+        const size_t i = base + threadIdx.x;
+        const uint32_t x = i < n ? cnt[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<1024>(x, total, s_tmp);
+        if (i < n) cnt[i] = running + ex;
+        running += total;
+    }
+    if (threadIdx.x == 0) *m_dev = running;
+}
+
+__global__ __launch_bounds__(kEmitBlock) void k_emit_write(
+    const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
+    const GpuView* __restrict__ views, int n_views, int64_t n_vp,
+    const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ pkey,
+    uint32_t* __restrict__ pid) {
+    __shared__ uint32_t s_tmp[kEmitBlock / kWave];
+    __shared__ uint32_t s_key[4 * kChunk];
+    __shared__ uint32_t s_id[4 * kChunk];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
+    uint32_t vals[kEmitItems];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i) {
+        vals[i] = (base + i < n_vp) ? zval[base + i] : 0u;
+        cnt += __popc(vals[i] >> 28);
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i) {
+        const uint32_t mask = vals[i] >> 28;
+        if (mask == 0u) continue;
+        const uint32_t vp = vals[i] & kVpMask;
+        const PointRec r = rec[vp];
+        const int v = n_views == 1 ? 0
+                                   : find_view(views, n_views, (int64_t)vp,
+                                               [](const GpuView& g) { return g.vpoint_offset; });
+        const GpuView& V = views[v];
+        const int x0 = anc_x0(r.anc), y0 = anc_y0(r.anc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!((mask >> c) & 1u)) continue;
+            const int64_t q = V.pixel_offset + (int64_t)(y0 + (c >> 1)) * V.W + (x0 + (c & 1));
+            s_key[pos] = (uint32_t)q;
+            s_id[pos] = 4u * vp + (uint32_t)c;
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const uint32_t off = chunk_off[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < total; j += kEmitBlock) {
+        pkey[off + j] = s_key[j];
+        pid[off + j] = s_id[j];
+    }
+}
+
+void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+                 int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev, uint32_t* pkey,
+                 uint32_t* pid, hipStream_t s) {
+    const size_t chunks = emit_chunks(n_vp);
+    if (chunks == 0) {
+        launch_fill_u32(m_dev, 0u, 1, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_emit_count, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
+                       n_vp, chunk_cnt);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev);
+    hipLaunchKernelGGL(k_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
+                       rec, views, n_views, n_vp, chunk_cnt, pkey, pid);
+}
+
+}  // namespace inpc

@@ -1,0 +1,284 @@
+// Stable LSD radix sort of (u32 key, u32 value) pairs for gfx950 (the
+// RadixSortPairs step of Algorithm 1), and the per-pixel segment ranges of
+// the sorted fragment list.
+//
+// Each pass over a digit of D bits is reduce-then-scan:
+//   upsweep   one LDS histogram per tile (wave-level digit matching, so a
+//             digit shared by many lanes costs one LDS update per wave);
+//   scan      per-digit exclusive scan over tiles, then over digits;
+//   downsweep the tile is ranked stably inside LDS (per-wave multisplit,
+//             cross-wave prefix per digit), staged in LDS in digit order and
+//             written out so that consecutive lanes write consecutive
+//             addresses of one digit's run.
+// The live element count may sit in device memory (fragment count M), so a
+// pass needs no host round trip; blocks past the live count exit at once.
+#include "internal.h"
+
+namespace inpc {
+
+constexpr int kSortBlock = 256;
+
+static inline size_t tiles_for(int items, int64_t n) {
+    const int64_t tile = (int64_t)kSortBlock * items;
+    return (size_t)((n + tile - 1) / tile);
+}
+
+size_t sort_counts_words(int digit, int items, int64_t n_bound) {
+    return ((size_t)1 << digit) * (tiles_for(items, n_bound) + 1) + ((size_t)1 << digit);
+}
+
+int radix_passes(int digit, int bits) { return bits <= 0 ? 0 : (bits + digit - 1) / digit; }
+
+__device__ __forceinline__ uint32_t live_count(const uint32_t* n_dev, uint32_t n_bound) {
+    if (!n_dev) return n_bound;
+    const uint32_t n = *n_dev;
+    return n < n_bound ? n : n_bound;
+}
+
+template <int D, int ITEMS>
+__global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
+                                                              const uint32_t* __restrict__ n_dev,
+                                                              uint32_t n_bound, int shift,
+                                                              uint32_t* __restrict__ counts,
+                                                              uint32_t stride) {
+    constexpr int BINS = 1 << D;
+    constexpr int TILE = kSortBlock * ITEMS;
+    __shared__ uint32_t s_hist[BINS];
+    const uint32_t n = live_count(n_dev, n_bound);
+    const uint32_t tile = blockIdx.x;
+    if ((uint64_t)tile * TILE >= n) return;
+    for (int i = threadIdx.x; i < BINS; i += kSortBlock) s_hist[i] = 0;
+    __syncthreads();
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const uint32_t base = tile * TILE + w * (ITEMS * kWave);
+#pragma unroll 4
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (keys[idx] >> shift) & (BINS - 1) : 0u;
+        const uint64_t peers = match_digit<D>(d, valid);
+        if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_hist[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < BINS; i += kSortBlock) counts[(size_t)i * stride + tile] = s_hist[i];
+}
+
+// Row-wise exclusive scan of counts[bin][0..tiles) in place; bin totals out.
+__global__ __launch_bounds__(kSortBlock) void k_scan_rows(uint32_t* __restrict__ counts,
+                                                          uint32_t stride,
+                                                          const uint32_t* __restrict__ n_dev,
+                                                          uint32_t n_bound, uint32_t tile_size,
+                                                          uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_tmp[kSortBlock / kWave];
+    const uint32_t n = live_count(n_dev, n_bound);
+    const uint32_t tiles = (n + tile_size - 1) / tile_size;
+    uint32_t* row = counts + (size_t)blockIdx.x * stride;
+    uint32_t running = 0;
+    for (uint32_t base = 0; base < tiles; base += kSortBlock * 4) {
+        const uint32_t i0 = base + threadIdx.x * 4;
+        uint32_t v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = (i0 + j < tiles) ? row[i0 + j] : 0u;
+        const uint32_t s = v[0] + v[1] + v[2] + v[3];
+        uint32_t total;
+        uint32_t ex = block_excl_sum<kSortBlock>(s, total, s_tmp) + running;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < tiles) row[i0 + j] = ex;
+            ex += v[j];
+        }
+        running += total;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = running;
+}
+
+// Exclusive scan of the bin totals (<= 4096 bins) in one block.
+__global__ __launch_bounds__(1024) void k_scan_bins(uint32_t* __restrict__ totals, int bins) {
+    __shared__ uint32_t s_tmp[1024 / kWave];
+    uint32_t running = 0;
+    for (int base = 0; base < bins; base += 1024) {
+        const int i = base + threadIdx.x;
+        const uint32_t x = i < bins ? totals[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_sum<1024>(x, total, s_tmp);
+        if (i < bins) totals[i] = running + ex;
+        running += total;
+    }
+}
+
+template <int D, int ITEMS>
+__global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev,
+    uint32_t n_bound, int shift, const uint32_t* __restrict__ row_prefix, uint32_t stride,
+    const uint32_t* __restrict__ bin_base) {
+    constexpr int BINS = 1 << D;
+    constexpr int WAVES = kSortBlock / kWave;
+    constexpr int TILE = kSortBlock * ITEMS;
+    __shared__ uint32_t s_cnt[WAVES][BINS];   // per-wave digit counts, then cross-wave offsets
+    __shared__ uint32_t s_start[BINS];        // first LDS slot of each digit in the tile
+    __shared__ uint32_t s_dst[BINS];          // global start of each digit for this tile
+    __shared__ uint32_t s_key[TILE];
+    __shared__ uint32_t s_val[TILE];
+    __shared__ uint32_t s_tmp[WAVES];
+
+    const uint32_t n = live_count(n_dev, n_bound);
+    const uint32_t tile = blockIdx.x;
+    if ((uint64_t)tile * TILE >= n) return;
+    for (int i = threadIdx.x; i < WAVES * BINS; i += kSortBlock) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const int w = threadIdx.x / kWave, lane = __lane_id();
+    const uint32_t base = tile * TILE + w * (ITEMS * kWave);
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        const bool valid = idx < n;
+        key[it] = valid ? kin[idx] : 0u;
+        val[it] = valid ? vin[idx] : 0u;
+    }
+    // Rows are processed in input order, so ranks within a wave are stable.
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        const bool valid = idx < n;
+        const uint32_t d = (key[it] >> shift) & (BINS - 1);
+        const uint64_t peers = match_digit<D>(d, valid);
+        const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
+        const int leader = valid ? (__ffsll((unsigned long long)peers) - 1) : lane;
+        uint32_t old = 0;
+        if (valid && below == 0u) {
+            old = s_cnt[w][d];
+            s_cnt[w][d] = old + (uint32_t)__popcll(peers);
+        }
+        old = __shfl(old, leader);
+        rank[it] = old + below;
+    }
+    __syncthreads();
+    // Cross-wave exclusive prefix per digit and digit totals of the tile.
+    uint32_t my_tot[(BINS + kSortBlock - 1) / kSortBlock];
+#pragma unroll
+    for (int j = 0; j < (BINS + kSortBlock - 1) / kSortBlock; ++j) {
+        const int d = threadIdx.x + j * kSortBlock;
+        uint32_t sum = 0;
+        if (d < BINS) {
+#pragma unroll
+            for (int ww = 0; ww < WAVES; ++ww) {
+                const uint32_t c = s_cnt[ww][d];
+                s_cnt[ww][d] = sum;
+                sum += c;
+            }
+        }
+        my_tot[j] = sum;
+    }
+    // Exclusive scan of digit totals over the block (digits are owned
+    // thread-major: thread t owns digits t, t+256, ...; scan in digit order).
+    {
+        uint32_t running = 0;
+#pragma unroll
+        for (int j = 0; j < (BINS + kSortBlock - 1) / kSortBlock; ++j) {
+            uint32_t total;
+            const uint32_t ex = block_excl_sum<kSortBlock>(my_tot[j], total, s_tmp);
+            const int d = threadIdx.x + j * kSortBlock;
+            if (d < BINS) {
+                s_start[d] = running + ex;
+                s_dst[d] = bin_base[d] + row_prefix[(size_t)d * stride + tile];
+            }
+            running += total;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        if (idx < n) {
+            const uint32_t d = (key[it] >> shift) & (BINS - 1);
+            const uint32_t slot = s_start[d] + s_cnt[w][d] + rank[it];
+            s_key[slot] = key[it];
+            s_val[slot] = val[it];
+        }
+    }
+    __syncthreads();
+    const uint32_t tile_n = (n - tile * TILE) < (uint32_t)TILE ? (n - tile * TILE) : (uint32_t)TILE;
+    for (uint32_t j = threadIdx.x; j < tile_n; j += kSortBlock) {
+        const uint32_t k = s_key[j];
+        const uint32_t d = (k >> shift) & (BINS - 1);
+        const uint32_t dst = s_dst[d] + (j - s_start[d]);
+        kout[dst] = k;
+        vout[dst] = s_val[j];
+    }
+}
+
+template <int D, int ITEMS>
+static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
+                      const uint32_t* n_dev, int64_t n_bound, int shift, uint32_t* counts,
+                      hipStream_t s) {
+    const size_t tiles = tiles_for(ITEMS, n_bound);
+    const uint32_t stride = (uint32_t)tiles + 1;
+    uint32_t* totals = counts + ((size_t)1 << D) * stride;
+    hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                       kin, n_dev, (uint32_t)n_bound, shift, counts, stride);
+    hipLaunchKernelGGL(k_scan_rows, dim3(1u << D), dim3(kSortBlock), 0, s, counts, stride, n_dev,
+                       (uint32_t)n_bound, (uint32_t)(kSortBlock * ITEMS), totals);
+    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, totals, 1 << D);
+    hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                       kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals);
+}
+
+using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const uint32_t*,
+                        int64_t, int, uint32_t*, hipStream_t);
+
+static PassFn pass_fn(int digit, int items) {
+#define INPC_CASE(D, I) \
+    if (digit == D && items == I) return &sort_pass<D, I>;
+    INPC_CASE(8, 8) INPC_CASE(8, 16)
+    INPC_CASE(10, 8) INPC_CASE(10, 16)
+    INPC_CASE(11, 8) INPC_CASE(11, 16)
+#undef INPC_CASE
+    return nullptr;
+}
+
+// Pass 0 reads (kin, vin) and writes (ka, va); later passes alternate
+// (ka, va) -> (kb, vb) -> (ka, va) ...  (kin, vin) may alias (kb, vb).
+void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
+                       uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s) {
+    const int passes = radix_passes(digit, bits);
+    if (n_bound == 0 || passes == 0) return;
+    PassFn fn = pass_fn(digit, items);
+    const uint32_t* ki = kin;
+    const uint32_t* vi = vin;
+    uint32_t *ko = ka, *vo = va;
+    for (int p = 0; p < passes; ++p) {
+        fn(ki, vi, ko, vo, n_dev, n_bound, p * digit, counts, s);
+        ki = ko;
+        vi = vo;
+        ko = (ko == ka) ? kb : ka;
+        vo = (vo == va) ? vb : va;
+    }
+}
+
+bool sort_valid(int digit, int items) { return pass_fn(digit, items) != nullptr; }
+
+// ------------------------------------------------------------ pixel ranges
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
+                                                const uint32_t* __restrict__ m_dev,
+                                                uint32_t m_bound, uint2* __restrict__ range) {
+    const uint32_t m = live_count(m_dev, m_bound);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) range[k].x = i;
+    if (i + 1 == m || keys[i + 1] != k) range[k].y = i + 1;
+}
+
+void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
+                   int64_t n_pixels, uint2* range, hipStream_t s) {
+    launch_fill_u32(reinterpret_cast<uint32_t*>(range), 0u, (size_t)n_pixels * 2, s);
+    if (m_bound == 0) return;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_bound + 255) / 256)), dim3(256), 0, s,
+                       pkey_sorted, m_dev, (uint32_t)m_bound, range);
+}
+
+}  // namespace inpc

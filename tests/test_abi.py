@@ -1,0 +1,148 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, answers size queries, and rejects bad arguments on the host
+before anything is enqueued."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2403_16862_amd as pr
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "inpc_raster.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(inpc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pr.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_version_and_error_strings():
+    L = pr.lib()
+    assert L.inpc_version() >= 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.inpc_error_string(code)
+
+
+def test_tuning_table_is_listed():
+    names = pr.tuning_table()
+    assert len(names) >= 4 and all(names)
+
+
+def cam(W=64, H=48):
+    return workloads.canonical_camera(W, H)
+
+
+def test_sizes_scale_with_points_and_pixels():
+    a = pr.plain_sizes(1000, cam(), 8, pr.INPC_F32, pr.INPC_SAVE)
+    b = pr.plain_sizes(4000, cam(), 8, pr.INPC_F32, pr.INPC_SAVE)
+    c = pr.plain_sizes(1000, cam(128, 96), 8, pr.INPC_F32, pr.INPC_SAVE)
+    assert all(x > 0 for x in a)
+    assert b[0] > a[0] and b[1] > a[1] and b[2] > a[2]
+    assert c[1] > a[1]
+    r = pr.plain_sizes(1000, cam(), 8, pr.INPC_F32, pr.INPC_RECOMPUTE)
+    assert r[1] < a[1]          # recompute keeps only per-pixel state
+    assert r[2] > a[2]          # and rebuilds the fragment lists in the backward
+
+
+def test_sizes_zero_points():
+    a = pr.plain_sizes(0, cam(), 4, pr.INPC_F32, pr.INPC_SAVE)
+    assert a[1] > 0
+
+
+def _call_sizes(n=10, F=4, fdt=0, mode=0, c=None):
+    cc = pr.c_camera(c or cam())
+    x = ctypes.c_size_t()
+    return pr.lib().inpc_plain_sizes(n, ctypes.byref(cc), F, fdt, mode, ctypes.byref(x), None, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(F=0), -3), (dict(F=65), -3), (dict(fdt=2), -1), (dict(mode=3), -1), (dict(n=-1), -1),
+    (dict(n=1 << 28), -4),
+])
+def test_size_query_rejects(kw, code):
+    assert _call_sizes(**kw) == code
+
+
+def test_camera_validation():
+    c = cam()
+    bad = [dict(width=0), dict(width=20000), dict(height=-3), dict(near=2.0, far=1.0),
+           dict(near=-0.5), dict(fx=float("nan")), dict(far=float("nan"))]
+    for b in bad:
+        d = c.as_dict()
+        d.update(b)
+        rc = _call_sizes(c=d)
+        assert rc in (-1, -3), (b, rc)
+    assert pr.lib().inpc_plain_sizes(10, None, 4, 0, 0, None, None, None) == -1
+
+
+FAKE = 1 << 20   # never dereferenced: every call below fails validation first
+
+
+def _fwd(n=100, F=4, st=None, ws_bytes=None, saved_bytes=None, image=FAKE, feat=FAKE, saved=FAKE,
+         ws=FAKE):
+    c = pr.c_camera(cam())
+    fws, sv, _ = pr.plain_sizes(n, cam(), F, 0, 0)
+    st = st or pr.c_settings(1e-4, 0, -1)
+    return pr.lib().inpc_rasterize_fwd(FAKE, feat, 0, FAKE, n, F, ctypes.byref(c), ctypes.byref(st),
+                                       image, FAKE, saved, sv if saved_bytes is None else saved_bytes,
+                                       ws, fws if ws_bytes is None else ws_bytes, None)
+
+
+def test_forward_rejects_small_workspace():
+    assert _fwd(ws_bytes=16) == -2
+    assert _fwd(saved_bytes=16) == -2
+
+
+@pytest.mark.parametrize("st", [pr.c_settings(-1.0, 0, -1), pr.c_settings(float("inf"), 0, -1),
+                                pr.c_settings(1e-4, 5, -1), pr.c_settings(1e-4, 0, 999)])
+def test_forward_rejects_settings(st):
+    assert _fwd(st=st) == -1
+
+
+def test_forward_rejects_reserved_field():
+    st = pr.c_settings(1e-4, 0, -1)
+    st.reserved = 1
+    assert _fwd(st=st) == -1
+
+
+def test_forward_rejects_null_and_misaligned():
+    assert _fwd(image=None) == -1
+    assert _fwd(image=FAKE + 4) == -1       # image must be 16-byte aligned
+    assert _fwd(feat=FAKE + 8) == -1        # features must be 16-byte aligned
+    assert _fwd(saved=FAKE + 16) == -1      # buffers must be 256-byte aligned
+
+
+def test_batched_views_must_be_packed_in_order():
+    c1, c2 = cam(32, 16), cam(16, 8)
+    views = pr.make_views([c1, c2], [0, 50], [50, 50])
+    fws, sv, bws = pr.batched_sizes(views, 2, 100, 4, 0, 0)
+    assert fws > 0
+    views[1].pixel_offset += 1
+    with pytest.raises(pr.InpcError):
+        pr.batched_sizes(views, 2, 100, 4, 0, 0)
+    views = pr.make_views([c1, c2], [0, 60], [50, 50])   # view 2 runs past the point arrays
+    with pytest.raises(pr.InpcError):
+        pr.batched_sizes(views, 2, 100, 4, 0, 0)
+
+
+def test_view_grads_validation():
+    views = pr.make_views([cam(8, 8)], [0], [10])
+    L = pr.lib()
+    rc = L.inpc_sum_view_grads(views, 1, 10, 4, FAKE, FAKE, FAKE, FAKE, FAKE + 8, 4096, None)
+    assert rc == -1   # workspace pointer not 256-aligned
+    rc = L.inpc_sum_view_grads(views, 1, 10, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 8, None)
+    assert rc == -2   # workspace smaller than the view table
