@@ -1,0 +1,259 @@
+"""Benchmark of the differentiable bilinear point rasterizer on one MI355X.
+
+Headline: forward + backward (through torch.autograd.Function) of 8M
+synthetic points at 1920x1080 with 16 float32 features, in fragments per
+second (fragments = splats the forward emits).  Also reported on the same
+JSON line: per-stage timings measured with HIP events inside the timed
+steps, the roofline figure of the dominant kernel, the CPU oracle's rate on
+the same workload, and the batched bfloat16 path (16 views of uneven size,
+one HIP-graph replay) against 16 sequential float32 plain calls.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tuning", type=int, default=-1)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def stage_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses):
+    """Compulsory bytes per step of each stage (each input read once, each
+    output written once; see the design notes for the derivation)."""
+    return {
+        "project": 12 * N + 4 * N + 16 * N + 8 * N,
+        "sort_upsweep": zpasses * 4 * N + ppasses * 4 * M,
+        "sort_downsweep": zpasses * 16 * N + ppasses * 16 * M,
+        "emit": 4 * N + 4 * N + 16 * N_vis + 8 * M,
+        "ranges": 8 * P + 4 * M,
+        "blend_fwd": 8 * P + 4 * M_b + (16 + F * feat_bytes) * N_vis + (4 * F + 4 + 16) * P + 4 * M_b,
+        "clear_records": 32 * N,
+        "blend_bwd": 8 * P + 16 * P + 4 * M_b + 4 * M_b + (16 + F * feat_bytes) * N_vis + 4 * F * P + 8 * M_b,
+        "point_reduce": 16 * N + 32 * N + 4 * F * min(P, 4 * N_vis) + (4 * F + 4) * N,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this rasterizer runs on one GPU; multi-GPU runs are not supported "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2403_16862_amd as pr
+    import workloads
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    s = workloads.config3()
+    log(f"generated config 3 in {time.time() - t0:.1f}s: N={s.n} {s.cam.width}x{s.cam.height} F={s.F}")
+    x = torch.from_numpy(s.xyz).to(dev)
+    f = torch.from_numpy(s.feat).to(dev).requires_grad_(True)
+    o = torch.from_numpy(s.opa).to(dev).requires_grad_(True)
+    g = torch.from_numpy(s.g_img).to(dev)
+
+    def step():
+        f.grad = None
+        o.grad = None
+        img, tf = pr.rasterize(x, f, o, s.cam, 1e-4, "save", args.tuning)
+        torch.autograd.backward([img], [g])
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    pr.profile_begin()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    stages = pr.profile_end()
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+
+    # fragment counts of this workload (deterministic; measured outside the timed region)
+    _, _, st = pr.rasterize_forward(x, f.detach(), o.detach(), s.cam, 1e-4, "save", args.tuning,
+                                    keep_workspace=True)
+    keys, ids, nb = pr.debug_fragments(st)
+    M = int(keys.shape[0])
+    M_b = int(nb.astype(np.int64).sum())
+    N_vis = int(np.unique(ids >> 2).size)
+    del keys, ids, st
+    P = s.cam.width * s.cam.height
+    value = M / (ms_per_step * 1e-3)
+
+    tn = pr.tuning_table()
+    tid = args.tuning if args.tuning >= 0 else pr.lib().inpc_tuning_for(
+        pr.make_views([s.cam], [0], [s.n]), 1, s.n, s.F, 0)
+    zdig = 8 if tn[tid].startswith("zsort 8") else (10 if tn[tid].startswith("zsort 10") else 11)
+    pdig = 8 if "pixel sort 8" in tn[tid] else 11
+    zpasses = -(-32 // zdig)
+    pbits = max(1, (P - 1).bit_length())
+    ppasses = -(-pbits // pdig)
+    model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses)
+    per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in stages.items() if v[1] > 0}
+    leaf = {k: v for k, v in per_step.items() if k in model}
+    dom = max(leaf, key=lambda k: leaf[k][0])
+    dom_ms = leaf[dom][0]
+    launches = leaf[dom][1]
+    achieved = model[dom] / (dom_ms * 1e-3) / 1e9
+    total_model = sum(model[k] for k in leaf)
+    traffic_file = os.path.join(ROOT, "profiles", "traffic_config3.json")
+    traffic = None
+    if os.path.exists(traffic_file):
+        tr = json.load(open(traffic_file))
+        if tr.get("kernel_stage") == dom and tr.get("valid", False):
+            traffic = tr.get("bytes_per_step")
+    roofline = {
+        "bound": "hbm", "kernel": dom, "launches_per_step": launches,
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes_per_step": int(model[dom]),
+        "traffic": traffic,
+    }
+    result = {
+        "metric": "fwd+bwd fragments/sec and HBM GB/s, 8M pts @1920x1080, batched vs plain",
+        "value": round(value, 1),
+        "unit": "fragments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "8M clustered points, 1920x1080, F=16 float32, random look-at camera, "
+                               "forward+backward through torch.autograd.Function",
+                   "points": s.n, "width": s.cam.width, "height": s.cam.height, "features": s.F,
+                   "fragments": M, "blended_fragments": M_b, "visible_points": N_vis,
+                   "t_threshold": 1e-4, "tuning": tn[tid]},
+        "model_gbs": round(total_model / (ms_per_step * 1e-3) / 1e9, 1),
+        "stages_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items()},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        import oracle
+        log("cpu baseline: oracle on the full workload (fragments + forward + backward)")
+        t0 = time.perf_counter()
+        L = oracle.fragments(s.xyz, s.cam)
+        fw = oracle.blend_forward(L, s.opa, s.feat, 1e-4)
+        oracle.blend_backward(L, s.opa, s.feat, fw["n_blended"], s.g_img)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": round(L.m / dt, 1), "unit": "fragments/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"whole workload once: {L.m} fragments, fwd+bwd in {dt:.2f} s",
+        }
+        del L, fw
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(pr, torch, np, workloads, log)
+
+    if args.calib_copy:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+    print(json.dumps(result), flush=True)
+
+
+def bench_batched(pr, torch, np, workloads, log, reps=5):
+    """16 views, BF16 features, one graph replay vs 16 plain FP32 calls."""
+    t0 = time.time()
+    b = workloads.config4()
+    log(f"generated config 4 in {time.time() - t0:.1f}s: {len(b.cams)} views, {int(sum(b.point_count))} points")
+    dev = "cuda:0"
+    x = torch.from_numpy(b.xyz).to(dev)
+    f32 = torch.from_numpy(b.feat).to(dev)
+    fbf = f32.to(torch.bfloat16)
+    o = torch.from_numpy(b.opa).to(dev)
+    g = torch.cat([torch.from_numpy(gi.reshape(-1, b.F)) for gi in b.g_imgs]).to(dev)
+    views = pr.make_views(b.cams, b.point_offset, b.point_count)
+    step = pr.BatchedStep(x, fbf, o, views, g)
+    best, best_ms = pr.autotune(x, fbf, o, views, g_img=g, repeats=2)
+    step = pr.BatchedStep(x, fbf, o, views, g, tuning_id=best)
+    step.capture()
+    for _ in range(2):
+        step.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    t_batched = e0.elapsed_time(e1) / reps
+    # plain: 16 sequential FP32 single-view forward+backward calls on the same inputs
+    plain = []
+    offs = np.cumsum([0] + [c.width * c.height for c in b.cams])
+    for v, cam in enumerate(b.cams):
+        sl = slice(b.point_offset[v], b.point_offset[v] + b.point_count[v])
+        plain.append((x[sl].contiguous(), f32[sl].contiguous(), o[sl].contiguous(), cam,
+                      g[offs[v]:offs[v + 1]].contiguous()))
+
+    def run_plain():
+        for xv, fv, ov, cam, gv in plain:
+            img, tf, st = pr.rasterize_forward(xv, fv, ov, cam, 1e-4, "save", -1)
+            pr.rasterize_backward(xv, fv, ov, st, gv)
+
+    run_plain()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        run_plain()
+    e1.record()
+    torch.cuda.synchronize()
+    t_plain = e0.elapsed_time(e1) / reps
+    M = pr.fragment_count(step.state())
+    # accuracy of the batched BF16 image vs the plain FP32 image of each view
+    img32 = []
+    for xv, fv, ov, cam, gv in plain:
+        im, tf, st = pr.rasterize_forward(xv, fv, ov, cam, 1e-4, "save", -1)
+        img32.append(im.reshape(-1, b.F))
+    img32 = torch.cat(img32)
+    err = (step.image - img32).abs().max().item()
+    log(f"batched: {t_batched:.3f} ms (graph replay, tuning {best}), plain 16 calls: {t_plain:.3f} ms")
+    return {"views": len(b.cams), "points": int(sum(b.point_count)), "pixels": int(offs[-1]),
+            "fragments": M, "ms_batched_bf16_graph": round(t_batched, 3),
+            "ms_plain_f32_sequential": round(t_plain, 3),
+            "speedup": round(t_plain / t_batched, 3),
+            "fragments_per_s_batched": round(M / (t_batched * 1e-3), 1),
+            "max_abs_image_diff_bf16_vs_f32": err, "tuning": best}
+
+
+if __name__ == "__main__":
+    main()

@@ -199,7 +199,7 @@ int inpc_tuning_for(const inpc_view_t *views_host, int32_t n_views, int64_t n_po
 
 /* Copy the sorted fragment list of a SAVE-mode forward to the host
  * (synchronises the stream).  saved and fwd_ws must be the buffers that
- * forward used, untouched since.  keys_host[i] = (global pixel << 32) | float32
+ * forward used, untouched since (fwd_ws may be NULL when keys_host is).  keys_host[i] = (global pixel << 32) | float32
  * bits of the view depth; ids_host[i] = 4*(view point) + corner, in sorted
  * order; *m_out = number of fragments (arrays of capacity cap; nothing is
  * copied if cap < *m_out).  n_blended_host (may be NULL) receives, per
@@ -210,6 +210,18 @@ int inpc_debug_fragments(const inpc_view_t *views_host, int32_t n_views, int64_t
                          const void *fwd_ws, size_t fwd_ws_bytes, uint64_t *keys_host,
                          uint32_t *ids_host, int64_t cap, int64_t *m_out,
                          uint32_t *n_blended_host, void *stream);
+
+/* Per-stage timing (measurement support, not part of the method).  Between
+ * inpc_profile_begin() and inpc_profile_end() every stage of the calls above
+ * records a pair of HIP events on its stream (so do not capture graphs while
+ * profiling).  inpc_profile_end() waits for them and writes, per stage, the
+ * summed milliseconds and the number of timed launches into arrays of
+ * inpc_profile_stage_count() entries (either may be NULL).  Process-wide;
+ * not meant for concurrent use from several host threads. */
+int inpc_profile_stage_count(void);
+const char *inpc_profile_stage_name(int32_t stage);
+int inpc_profile_begin(void);
+int inpc_profile_end(double *total_ms, int64_t *launches);
 
 const char *inpc_error_string(int code);
 const char *inpc_last_hip_error(void);

@@ -91,6 +91,10 @@ def lib():
         "inpc_tuning_for": [view_p, i32, i64, i32, i32],
         "inpc_debug_fragments": [view_p, i32, i64, i32, i32, P, sz, P, sz, P, P, i64,
                                  ctypes.POINTER(ctypes.c_int64), P, P],
+        "inpc_profile_stage_count": [],
+        "inpc_profile_stage_name": [i32],
+        "inpc_profile_begin": [],
+        "inpc_profile_end": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "inpc_error_string": [ctypes.c_int],
         "inpc_last_hip_error": [],
         "inpc_version": [],
@@ -100,6 +104,7 @@ def lib():
         fn.argtypes = args
         fn.restype = ctypes.c_int
     L.inpc_tuning_name.restype = ctypes.c_char_p
+    L.inpc_profile_stage_name.restype = ctypes.c_char_p
     L.inpc_error_string.restype = ctypes.c_char_p
     L.inpc_last_hip_error.restype = ctypes.c_char_p
     _lib = L
@@ -408,3 +413,104 @@ def debug_fragments(state: ForwardState):
                                   ids.ctypes.data_as(ctypes.c_void_p), m.value, ctypes.byref(m), None,
                                   _stream()), "inpc_debug_fragments")
     return keys, ids, nb
+
+
+# --------------------------------------------------------------- stage timing
+def profile_begin():
+    _check(lib().inpc_profile_begin(), "inpc_profile_begin")
+
+
+def profile_end():
+    """{stage name: (total ms, timed launches)} since profile_begin()."""
+    L = lib()
+    n = L.inpc_profile_stage_count()
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(L.inpc_profile_end(ms, cnt), "inpc_profile_end")
+    return {L.inpc_profile_stage_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
+
+
+def fragment_count(state: ForwardState) -> int:
+    """Number of splats the forward emitted (synchronises the stream)."""
+    m = ctypes.c_int64()
+    ws = state.fwd_ws
+    _check(lib().inpc_debug_fragments(state.views, state.n_views, state.n_points, state.F, state.fdt,
+                                      _ptr(state.saved), state.saved.numel(),
+                                      _ptr(ws), ws.numel() if ws is not None else 0, None, None, 0,
+                                      ctypes.byref(m), None, _stream()), "fragment_count")
+    return int(m.value)
+
+
+# ------------------------------------------------ batched step with HIP graphs
+class BatchedStep:
+    """Forward + backward of many views on static device buffers.
+
+    ``run()`` enqueues the batched forward and backward eagerly; ``capture()``
+    records the same launch sequence once into a HIP graph (through
+    torch.cuda.CUDAGraph) and ``replay()`` relaunches it.  No allocation,
+    host synchronisation or memset happens inside the step, so the recorded
+    graph is replayable; inputs are read from and outputs written to the
+    tensors given at construction.
+    """
+
+    def __init__(self, xyz, feat, opa, views, g_img, t_threshold: float = 1e-4, mode="save",
+                 tuning_id: int = -1, g_t=None):
+        self.xyz, self.feat, self.opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+        self.views = views
+        self.n_views = len(views)
+        self.N, self.F, self.fdt = int(xyz.shape[0]), int(feat.shape[1]), _fdt(feat)
+        m = _mode(mode)
+        self.settings = c_settings(t_threshold, m, tuning_id)
+        fws, sv, bws = batched_sizes(views, self.n_views, self.N, self.F, self.fdt, m)
+        dev = xyz.device
+        self.saved = _buffer(sv, dev)
+        self.fwd_ws = _buffer(fws, dev)
+        self.bwd_ws = _buffer(bws, dev)
+        self.P = sum(views[i].cam.width * views[i].cam.height for i in range(self.n_views))
+        self.nvp = sum(int(views[i].point_count) for i in range(self.n_views))
+        self.image = torch.empty((self.P, self.F), dtype=torch.float32, device=dev)
+        self.t_final = torch.empty((self.P,), dtype=torch.float32, device=dev)
+        self.g_img = g_img.contiguous().float()
+        self.g_t = None if g_t is None else g_t.contiguous().float()
+        self.grad_feat = torch.empty((self.nvp, self.F), dtype=torch.float32, device=dev)
+        self.grad_opa = torch.empty((self.nvp,), dtype=torch.float32, device=dev)
+        self.graph = None
+
+    def forward(self):
+        _check(lib().inpc_rasterize_fwd_batched(
+            _ptr(self.xyz), _ptr(self.feat), self.fdt, _ptr(self.opa), self.N, self.F, self.views,
+            self.n_views, ctypes.byref(self.settings), _ptr(self.image), _ptr(self.t_final),
+            _ptr(self.saved), self.saved.numel(), _ptr(self.fwd_ws), self.fwd_ws.numel(), _stream()),
+            "inpc_rasterize_fwd_batched")
+
+    def backward(self):
+        _check(lib().inpc_rasterize_bwd_batched(
+            _ptr(self.xyz), _ptr(self.feat), self.fdt, _ptr(self.opa), self.N, self.F, self.views,
+            self.n_views, ctypes.byref(self.settings), _ptr(self.saved), self.saved.numel(),
+            _ptr(self.g_img), _ptr(self.g_t), _ptr(self.grad_feat), _ptr(self.grad_opa),
+            _ptr(self.bwd_ws), self.bwd_ws.numel(), _stream()), "inpc_rasterize_bwd_batched")
+
+    def run(self):
+        self.forward()
+        self.backward()
+
+    def capture(self):
+        """Record forward + backward into a HIP graph (after one eager warm-up run)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.run()
+        torch.cuda.synchronize()
+        return self
+
+    def replay(self):
+        self.graph.replay()
+
+    def state(self) -> ForwardState:
+        return ForwardState(self.saved, self.fwd_ws, self.settings, self.views, self.n_views, self.N,
+                            self.F, self.fdt)

@@ -140,7 +140,7 @@ struct Carver {
 // splat ids and per-pixel ranges; it lives in ``saved`` in SAVE mode and in
 // the workspace of whichever pass builds it in RECOMPUTE mode.
 struct FragOffsets {
-    size_t rec, ids, range;
+    size_t rec, ids, range, tk;   // tk: T_k of every blended splat, by sorted slot
 };
 struct BuildOffsets {  // transient buffers of the fragment build
     size_t views, scalars, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, chunks, pk_a, pk_b, pv_other, counts;
@@ -169,6 +169,7 @@ static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
     f.rec = c.take((size_t)pb.n_vp * sizeof(PointRec));
     f.ids = c.take((size_t)4 * pb.n_vp * 4);
     f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
+    f.tk = c.take((size_t)4 * pb.n_vp * 4);
 }
 
 static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
@@ -213,6 +214,57 @@ static T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
+// ------------------------------------------------------------ profiling
+static const char* kStageNames[kNumStages] = {
+    "project", "depth_sort", "emit", "pixel_sort", "ranges", "blend_fwd", "clear_records",
+    "blend_bwd", "point_reduce", "sort_upsweep", "sort_scan", "sort_downsweep", "view_grads"};
+
+const char* stage_name(int st) { return (st >= 0 && st < kNumStages) ? kStageNames[st] : ""; }
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+struct ProfRec {
+    int stage;
+    hipEvent_t a, b;
+};
+static std::vector<hipEvent_t> g_prof_pool;
+static size_t g_prof_used = 0;
+static std::vector<std::pair<int, hipEvent_t>> g_prof_stack;
+static std::vector<ProfRec> g_prof_recs;
+
+static hipEvent_t prof_event() {
+    if (g_prof_used == g_prof_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_prof_pool.push_back(e);
+    }
+    return g_prof_pool[g_prof_used++];
+}
+
+void prof_begin(int st, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t e = prof_event();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    g_prof_stack.push_back({st, e});
+}
+
+void prof_end(int st, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (size_t i = g_prof_stack.size(); i-- > 0;) {
+        if (g_prof_stack[i].first != st) continue;
+        hipEvent_t e = prof_event();
+        if (e) {
+            (void)hipEventRecord(e, s);
+            g_prof_recs.push_back({st, g_prof_stack[i].second, e});
+        }
+        g_prof_stack.erase(g_prof_stack.begin() + (long)i);
+        return;
+    }
+}
+
 // ------------------------------------------------------------ autotuner
 static std::mutex g_tune_mu;
 static std::map<std::string, int> g_tune_cache;
@@ -253,14 +305,20 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     PointRec* rec = at<PointRec>(frag_base, fo.rec);
     uint32_t* zk_in = at<uint32_t>(build_base, bo.zk_in);
     uint32_t* zv_in = at<uint32_t>(build_base, bo.zv_in);
-    launch_project(xyz, opacity, views, nv, pb.n_vp, rec, zk_in, zv_in, s);
+    {
+        ProfScope p(kStProject, s);
+        launch_project(xyz, opacity, views, nv, pb.n_vp, rec, zk_in, zv_in, s);
+    }
     uint32_t* zk_a = at<uint32_t>(build_base, bo.zk_a);
     uint32_t* zv_a = at<uint32_t>(build_base, bo.zv_a);
     uint32_t* zk_b = at<uint32_t>(build_base, bo.zk_b);
     uint32_t* zv_b = at<uint32_t>(build_base, bo.zv_b);
     uint32_t* counts = at<uint32_t>(build_base, bo.counts);
-    launch_radix_sort(tn.zdigit, tn.sort_items, 32, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
-                      pb.n_vp, counts, s);
+    {
+        ProfScope p(kStDepthSort, s);
+        launch_radix_sort(tn.zdigit, tn.sort_items, 32, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
+                          pb.n_vp, counts, s);
+    }
     const int zp = radix_passes(tn.zdigit, 32);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
 
@@ -273,12 +331,21 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* pk_b = at<uint32_t>(build_base, bo.pk_b);
     uint32_t* pv_a = (pp & 1) ? ids_final : pv_other;
     uint32_t* pv_b = (pp & 1) ? pv_other : ids_final;
-    launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
-                pv_b, s);
-    launch_radix_sort(tn.pdigit, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
-                      m_dev, 4 * pb.n_vp, counts, s);
+    {
+        ProfScope p(kStEmit, s);
+        launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
+                    pv_b, s);
+    }
+    {
+        ProfScope p(kStPixelSort, s);
+        launch_radix_sort(tn.pdigit, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
+                          m_dev, 4 * pb.n_vp, counts, s);
+    }
     const uint32_t* pk_sorted = (pp & 1) ? pk_a : pk_b;
-    launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, pb.n_pixels, at<uint2>(frag_base, fo.range), s);
+    {
+        ProfScope p(kStRanges, s);
+        launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, pb.n_pixels, at<uint2>(frag_base, fo.range), s);
+    }
 }
 
 // ------------------------------------------------------------- forward
@@ -293,10 +360,12 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
     build_fragments(pb, tn, xyz, opacity, frag_base, fo, ws, L.fwd_build, m_dev, s);
+    ProfScope p(kStBlendFwd, s);
     launch_blend_fwd(pb.F, pb.fdt, tn.blend_wave_x, at<GpuView>(ws, L.fwd_build.views),
                      (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
                      at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
-                     image, t_final, at<PixelState>(saved, L.s_state), s);
+                     image, t_final, at<PixelState>(saved, L.s_state),
+                     pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr, s);
     return check_launch("inpc forward");
 }
 
@@ -327,12 +396,21 @@ static int backward(const Problem& pb, int tid, const float* xyz, const void* fe
         fo = &L.bwd_frag;
     }
     float2* frec = at<float2>(ws, L.b_frec);
-    launch_fill_u32(reinterpret_cast<uint32_t*>(frec), 0u, (size_t)8 * pb.n_vp, s);
+    {
+        ProfScope p(kStClearRecords, s);
+        launch_fill_u32(reinterpret_cast<uint32_t*>(frec), 0u, (size_t)8 * pb.n_vp, s);
+    }
+    {
+    ProfScope p(kStBlendBwd, s);
     launch_blend_bwd(pb.F, pb.fdt, tn.blend_wave_x, views, (int)pb.views.size(), pb.n_tiles,
                      at<const uint2>(const_cast<void*>(frag_base), fo->range),
                      at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
                      at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat,
-                     at<const PixelState>(sv, L.s_state), g_img, g_t, frec, s);
+                     at<const PixelState>(sv, L.s_state), g_img, g_t,
+                     at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
+                     frec, s);
+    }
+    ProfScope p(kStPointReduce, s);
     launch_point_reduce(pb.F, views, (int)pb.views.size(), pb.n_vp,
                         at<const PointRec>(const_cast<void*>(frag_base), fo->rec), frec, g_img,
                         grad_feat, grad_opa, s);
@@ -549,9 +627,10 @@ int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_po
     Problem pb;
     int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
     if (rc) return rc;
-    if (!saved || !fwd_ws || !m_out) return INPC_EINVAL;
+    if (!saved || !m_out) return INPC_EINVAL;
     const Layout L = make_layout(pb);
-    if (saved_bytes < L.saved_bytes || fwd_ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
+    if (saved_bytes < L.saved_bytes) return INPC_EWORKSPACE;
+    if (keys_host && (!fwd_ws || fwd_ws_bytes < L.fwd_bytes)) return INPC_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments sync");
@@ -698,6 +777,45 @@ int inpc_autotune(const float* xyz, const void* feat, int32_t fdt, const float* 
     }
     if (best_ms) *best_ms = best_t;
     return best;
+}
+
+
+int inpc_profile_stage_count(void) { return kNumStages; }
+
+const char* inpc_profile_stage_name(int32_t stage) { return stage_name(stage); }
+
+int inpc_profile_begin(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_recs.clear();
+    g_prof_stack.clear();
+    g_prof_used = 0;
+    g_prof_on = true;
+    return INPC_OK;
+}
+
+int inpc_profile_end(double* total_ms, int64_t* launches) {
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_on = false;
+        recs.swap(g_prof_recs);
+        g_prof_stack.clear();
+    }
+    for (int i = 0; i < kNumStages; ++i) {
+        if (total_ms) total_ms[i] = 0.0;
+        if (launches) launches[i] = 0;
+    }
+    for (const ProfRec& r : recs) {
+        const hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "inpc_profile_end");
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        if (total_ms) total_ms[r.stage] += ms;
+        if (launches) launches[r.stage] += 1;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_used = 0;
+    return INPC_OK;
 }
 
 }  // extern "C"

@@ -168,6 +168,7 @@ __device__ __forceinline__ void store_row(float* __restrict__ row, const float (
 // operation order as the projection defines it: w_x = ax for the right
 // column, 1 - ax for the left one.
 __device__ __forceinline__ void corner_factors(float ax, float ay, int c, float& wx, float& wy) {
+#pragma clang fp contract(off)
     wx = (c & 1) ? ax : 1.0f - ax;
     wy = (c & 2) ? ay : 1.0f - ay;
 }
@@ -176,6 +177,7 @@ __device__ __forceinline__ void corner_factors(float ax, float ay, int c, float&
 // complement is formed from the exact product (two error-free products via
 // fma), so it keeps full relative precision when alpha is close to one.
 __device__ __forceinline__ void splat_alpha(float opa, float wx, float wy, float& alpha, float& om) {
+#pragma clang fp contract(off)
     const float w_hi = wx * wy;
     const float w_lo = __builtin_fmaf(wx, wy, -w_hi);
     alpha = opa * w_hi;

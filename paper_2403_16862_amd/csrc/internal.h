@@ -22,6 +22,25 @@ struct Tuning {
 int tuning_count();
 const Tuning& tuning(int id);
 
+// -------------------------------------------------------------- profiling
+// Optional per-stage timing with HIP events on the launch stream (off by
+// default; see inpc_profile_begin/inpc_profile_end).  Stages may nest.
+enum Stage {
+    kStProject, kStDepthSort, kStEmit, kStPixelSort, kStRanges, kStBlendFwd, kStClearRecords,
+    kStBlendBwd, kStPointReduce, kStSortUpsweep, kStSortScan, kStSortDownsweep, kStViewGrads,
+    kNumStages
+};
+const char* stage_name(int stage);
+void prof_begin(int stage, hipStream_t s);
+void prof_end(int stage, hipStream_t s);
+
+struct ProfScope {
+    int st;
+    hipStream_t s;
+    ProfScope(int stage, hipStream_t stream) : st(stage), s(stream) { prof_begin(st, s); }
+    ~ProfScope() { prof_end(st, s); }
+};
+
 // ------------------------------------------------------------------ launchers
 void launch_upload_views(const GpuView* host_views, int n, GpuView* dev, hipStream_t s);
 
@@ -59,20 +78,18 @@ void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m
 // Per-pixel state kept from the forward blend for the backward.
 struct alignas(16) PixelState {
     uint32_t n_blended;  // splats blended before termination
-    uint32_t j_last;     // last blended index k with T_k > 0 (valid if n_blended > 0)
-    float t_last;        // T_{j_last}
-    uint32_t pad;
+    uint32_t pad0, pad1, pad2;
 };
 
 void launch_blend_fwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
-                      hipStream_t s);
+                      float* t_before, hipStream_t s);
 
 void launch_blend_bwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, const PixelState* state, const float* g_img,
-                      const float* g_t, float2* frec, hipStream_t s);
+                      const float* g_t, float* t_before, int rebuild_t, float2* frec, hipStream_t s);
 
 void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
                          const PointRec* rec, const float2* frec, const float* g_img,

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ ids, const PointRec* __restrict__ rec, const FT* __restrict__ feat,
     int Fd, float tau, float* __restrict__ image, float* __restrict__ t_final,
-    PixelState* __restrict__ state) {
+    PixelState* __restrict__ state, float* __restrict__ t_before) {
     const TileCoord tc = tile_pixel<WX>(views, n_views);
     if (!tc.inside) return;
     const int64_t pbase = tc.V->point_offset - tc.V->vpoint_offset;
@@ -94,8 +94,8 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
     float C[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) C[f] = 0.0f;
-    float T = 1.0f, t_last = 1.0f;
-    uint32_t n = 0, j_last = 0;
+    float T = 1.0f;
+    uint32_t n = 0;
     for (uint32_t i = r.x; i < r.y; ++i) {
         const uint32_t id = ids[i];
         const uint32_t vp = id >> 2;
@@ -108,10 +108,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
         const float ta = T * alpha;
 #pragma unroll
         for (int f = 0; f < FM; ++f) C[f] = __builtin_fmaf(ta, cf[f], C[f]);
-        if (T > 0.0f) {
-            j_last = n;
-            t_last = T;
-        }
+        if (t_before) t_before[i] = T;
         T = T * om;
         ++n;
         if (T < tau) break;
@@ -120,9 +117,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
     t_final[tc.q] = T;
     PixelState st;
     st.n_blended = n;
-    st.j_last = j_last;
-    st.t_last = t_last;
-    st.pad = 0;
+    st.pad0 = st.pad1 = st.pad2 = 0;
     state[tc.q] = st;
 }
 
@@ -130,45 +125,59 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
 // Reverse walk over the blended splats k = n-1 .. 0 of a pixel with the
 // scalar recurrence Y_k = alpha_k (g.c_k) + (1-alpha_k) Y_{k+1},
 // Y_n = g_T, so that dL/dalpha_k = T_k ((g.c_k) - Y_{k+1}) and
-// dL/dc_k = T_k alpha_k g.  T_k is recomputed backwards from the saved
-// T_{j_last} as T_k = T_{k+1} / (1 - alpha_k) (never dividing by zero:
-// T_{k+1} > 0 for k < j_last), and is exactly 0 after j_last.
+// dL/dc_k = T_k alpha_k g.  T_k is the forward's own float32 value: stored
+// by the forward blend (t_before, one word per blended splat), or, when
+// ``rebuild_t`` is set, recomputed here by the same forward recurrence in a
+// first walk over the pixel's splats (needs only the point records).
 // Writes the per-splat record (dL/dalpha_k, T_k alpha_k) at splat id.
 template <typename FT, int FM, bool DYN, int WX>
 __global__ __launch_bounds__(256) void k_blend_bwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ ids, const PointRec* __restrict__ rec, const FT* __restrict__ feat,
     int Fd, const PixelState* __restrict__ state, const float* __restrict__ g_img,
-    const float* __restrict__ g_t, float2* __restrict__ frec) {
+    const float* __restrict__ g_t, float* __restrict__ t_before, int rebuild_t,
+    float2* __restrict__ frec) {
     const TileCoord tc = tile_pixel<WX>(views, n_views);
     if (!tc.inside) return;
-    const PixelState st = state[tc.q];
-    if (st.n_blended == 0) return;
+    const uint32_t n = state[tc.q].n_blended;
+    if (n == 0) return;
     const int64_t pbase = tc.V->point_offset - tc.V->vpoint_offset;
     const uint32_t start = range[tc.q].x;
+    if (rebuild_t) {
+        float T = 1.0f;
+        for (uint32_t k = 0; k < n; ++k) {
+            const uint32_t id = ids[start + k];
+            const PointRec pr = rec[id >> 2];
+            float wx, wy, alpha, om;
+            corner_factors(pr.ax, pr.ay, (int)(id & 3u), wx, wy);
+            splat_alpha(pr.opa, wx, wy, alpha, om);
+            t_before[start + k] = T;
+            T = T * om;
+        }
+    }
     float g[FM];
     f32_row<FM, DYN>(g_img, tc.q, Fd, g);
-    float Y = g_t ? g_t[tc.q] : 0.0f;
-    float t_next = 0.0f;
-    for (int k = (int)st.n_blended - 1; k >= 0; --k) {
+    // The scalar chain (g.c, alpha, 1 - alpha, Y) runs in float64 registers:
+    // dL/dalpha is a difference of two nearly equal sums for most splats, and
+    // float64 keeps that cancellation from eating the result.  Inputs and the
+    // stored records stay float32.
+    double Y = g_t ? (double)g_t[tc.q] : 0.0;
+    for (int k = (int)n - 1; k >= 0; --k) {
         const uint32_t id = ids[start + k];
         const uint32_t vp = id >> 2;
         const PointRec pr = rec[vp];
         float cf[FM];
         feat_row<FT, FM, DYN>(feat, pbase + vp, Fd, cf);
-        float wx, wy, alpha, om;
+        float wx, wy;
         corner_factors(pr.ax, pr.ay, (int)(id & 3u), wx, wy);
-        splat_alpha(pr.opa, wx, wy, alpha, om);
-        float gc = 0.0f;
+        const double alpha = (double)pr.opa * ((double)wx * (double)wy);
+        const double om = 1.0 - alpha;
+        double gc = 0.0;
 #pragma unroll
-        for (int f = 0; f < FM; ++f) gc = __builtin_fmaf(g[f], cf[f], gc);
-        float Tk;
-        if ((uint32_t)k > st.j_last) Tk = 0.0f;
-        else if ((uint32_t)k == st.j_last) Tk = st.t_last;
-        else Tk = t_next / om;
-        frec[id] = make_float2(Tk * (gc - Y), Tk * alpha);
-        Y = __builtin_fmaf(alpha, gc, om * Y);
-        t_next = Tk;
+        for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)cf[f], gc);
+        const double Tk = (double)t_before[start + k];
+        frec[id] = make_float2((float)(Tk * (gc - Y)), (float)(Tk * alpha));
+        Y = __builtin_fma(alpha, gc, om * Y);
     }
 }
 
@@ -187,10 +196,11 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     if (vp >= n_vp) return;
     const PointRec pr = rec[vp];
     const uint32_t mask = anc_mask(pr.anc);
-    float gf[FM];
+    // float64 accumulators: the (at most four) corner terms often cancel.
+    double gf[FM];
 #pragma unroll
-    for (int f = 0; f < FM; ++f) gf[f] = 0.0f;
-    float go = 0.0f;
+    for (int f = 0; f < FM; ++f) gf[f] = 0.0;
+    double go = 0.0;
     if (mask != 0u) {
         const int v = n_views == 1 ? 0
                                    : find_view(views, n_views, vp,
@@ -206,16 +216,19 @@ __global__ __launch_bounds__(256) void k_point_reduce(
             if (!((mask >> c) & 1u)) continue;
             float wx, wy;
             corner_factors(pr.ax, pr.ay, c, wx, wy);
-            go = __builtin_fmaf(wx * wy, da[c], go);
+            go = __builtin_fma((double)wx * (double)wy, (double)da[c], go);
             const int64_t q = V.pixel_offset + (int64_t)(y0 + (c >> 1)) * V.W + (x0 + (c & 1));
             float g[FM];
             f32_row<FM, DYN>(g_img, q, Fd, g);
 #pragma unroll
-            for (int f = 0; f < FM; ++f) gf[f] = __builtin_fmaf(ta[c], g[f], gf[f]);
+            for (int f = 0; f < FM; ++f) gf[f] = __builtin_fma((double)ta[c], (double)g[f], gf[f]);
         }
     }
-    f32_store<FM, DYN>(grad_feat, vp, Fd, gf);
-    grad_opa[vp] = go;
+    float out[FM];
+#pragma unroll
+    for (int f = 0; f < FM; ++f) out[f] = (float)gf[f];
+    f32_store<FM, DYN>(grad_feat, vp, Fd, out);
+    grad_opa[vp] = (float)go;
 }
 
 // ------------------------------------------------ view -> point gradients
@@ -248,20 +261,20 @@ __global__ __launch_bounds__(256) void k_sum_view_grads(
 template <typename FT, int FM, bool DYN, int WX>
 static void blend_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range,
                         const uint32_t* ids, const PointRec* rec, const void* feat, int Fd, float tau,
-                        float* image, float* t_final, PixelState* state, hipStream_t s) {
+                        float* image, float* t_final, PixelState* state, float* t_before, hipStream_t s) {
     hipLaunchKernelGGL((k_blend_fwd<FT, FM, DYN, WX>), dim3((unsigned)n_tiles), dim3(256), 0, s, views,
                        n_views, range, ids, rec, reinterpret_cast<const FT*>(feat), Fd, tau, image,
-                       t_final, state);
+                       t_final, state, t_before);
 }
 
 template <typename FT, int FM, bool DYN, int WX>
 static void blend_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range,
                         const uint32_t* ids, const PointRec* rec, const void* feat, int Fd,
-                        const PixelState* state, const float* g_img, const float* g_t, float2* frec,
-                        hipStream_t s) {
+                        const PixelState* state, const float* g_img, const float* g_t, float* t_before,
+                        int rebuild_t, float2* frec, hipStream_t s) {
     hipLaunchKernelGGL((k_blend_bwd<FT, FM, DYN, WX>), dim3((unsigned)n_tiles), dim3(256), 0, s, views,
                        n_views, range, ids, rec, reinterpret_cast<const FT*>(feat), Fd, state, g_img,
-                       g_t, frec);
+                       g_t, t_before, rebuild_t, frec);
 }
 
 // Calls body.template operator()<FM, DYN>() for the compiled feature widths.
@@ -296,16 +309,16 @@ static void dispatch_wx(int wave_x, Body&& body) {
 void launch_blend_fwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
-                      hipStream_t s) {
+                      float* t_before, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_f(F, [&]<int FM, bool DYN>() {
         dispatch_wx(wave_x, [&]<int WX>() {
             if (feat_dtype == 1)
                 blend_fwd_t<__hip_bfloat16, FM, DYN, WX>(views, n_views, n_tiles, range, ids, rec, feat, F,
-                                                         tau, image, t_final, state, s);
+                                                         tau, image, t_final, state, t_before, s);
             else
                 blend_fwd_t<float, FM, DYN, WX>(views, n_views, n_tiles, range, ids, rec, feat, F, tau,
-                                                image, t_final, state, s);
+                                                image, t_final, state, t_before, s);
         });
     });
 }
@@ -313,16 +326,16 @@ void launch_blend_fwd(int F, int feat_dtype, int wave_x, const GpuView* views, i
 void launch_blend_bwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, const PixelState* state, const float* g_img,
-                      const float* g_t, float2* frec, hipStream_t s) {
+                      const float* g_t, float* t_before, int rebuild_t, float2* frec, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_f(F, [&]<int FM, bool DYN>() {
         dispatch_wx(wave_x, [&]<int WX>() {
             if (feat_dtype == 1)
                 blend_bwd_t<__hip_bfloat16, FM, DYN, WX>(views, n_views, n_tiles, range, ids, rec, feat, F,
-                                                         state, g_img, g_t, frec, s);
+                                                         state, g_img, g_t, t_before, rebuild_t, frec, s);
             else
                 blend_bwd_t<float, FM, DYN, WX>(views, n_views, n_tiles, range, ids, rec, feat, F, state,
-                                                g_img, g_t, frec, s);
+                                                g_img, g_t, t_before, rebuild_t, frec, s);
         });
     });
 }

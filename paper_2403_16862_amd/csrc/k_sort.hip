@@ -217,13 +217,22 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     const size_t tiles = tiles_for(ITEMS, n_bound);
     const uint32_t stride = (uint32_t)tiles + 1;
     uint32_t* totals = counts + ((size_t)1 << D) * stride;
-    hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
-                       kin, n_dev, (uint32_t)n_bound, shift, counts, stride);
-    hipLaunchKernelGGL(k_scan_rows, dim3(1u << D), dim3(kSortBlock), 0, s, counts, stride, n_dev,
-                       (uint32_t)n_bound, (uint32_t)(kSortBlock * ITEMS), totals);
-    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, totals, 1 << D);
-    hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
-                       kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals);
+    {
+        ProfScope p(kStSortUpsweep, s);
+        hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                           kin, n_dev, (uint32_t)n_bound, shift, counts, stride);
+    }
+    {
+        ProfScope p(kStSortScan, s);
+        hipLaunchKernelGGL(k_scan_rows, dim3(1u << D), dim3(kSortBlock), 0, s, counts, stride, n_dev,
+                           (uint32_t)n_bound, (uint32_t)(kSortBlock * ITEMS), totals);
+        hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, totals, 1 << D);
+    }
+    {
+        ProfScope p(kStSortDownsweep, s);
+        hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                           kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals);
+    }
 }
 
 using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const uint32_t*,
