@@ -56,6 +56,30 @@ def stage_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses):
     }
 
 
+def source_digest() -> str:
+    """sha256 over the HIP sources, to tell whether stored counters are stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2403_16862_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str, launches: float):
+    """HBM bytes per step of ``stage`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated with a 1 GiB copy), or None
+    if the summary does not cover that stage or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_config3.json")
+    if not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    if tr.get("source_sha256") != source_digest():
+        return None
+    b = tr.get("per_launch_bytes", {}).get(stage)
+    return None if b is None else int(b * launches)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -127,12 +151,7 @@ def main():
     launches = leaf[dom][1]
     achieved = model[dom] / (dom_ms * 1e-3) / 1e9
     total_model = sum(model[k] for k in leaf)
-    traffic_file = os.path.join(ROOT, "profiles", "traffic_config3.json")
-    traffic = None
-    if os.path.exists(traffic_file):
-        tr = json.load(open(traffic_file))
-        if tr.get("kernel_stage") == dom and tr.get("valid", False):
-            traffic = tr.get("bytes_per_step")
+    traffic = measured_traffic(dom, launches)
     roofline = {
         "bound": "hbm", "kernel": dom, "launches_per_step": launches,
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

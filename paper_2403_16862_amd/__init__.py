@@ -291,6 +291,7 @@ class _Rasterize(torch.autograd.Function):
                                          False, img_hw)
         ctx.state = state
         ctx.fold = fold
+        ctx.set_materialize_grads(False)
         ctx.save_for_backward(xyz, feat, opa)
         return image, t_final
 
@@ -298,6 +299,8 @@ class _Rasterize(torch.autograd.Function):
     def backward(ctx, g_img, g_t):
         xyz, feat, opa = ctx.saved_tensors
         st = ctx.state
+        if g_img is None and g_t is None:
+            return (None,) * 10
         if g_img is None:
             P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
             g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)

@@ -19,17 +19,17 @@ namespace inpc {
 
 // ------------------------------------------------------------ tuning table
 static const Tuning kTunings[] = {
-    {8, 8, 16, 8, "zsort 8-bit digits, pixel sort 8-bit digits, 4096-key tiles, 8x8 wave tiles"},
-    {11, 11, 16, 8, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
-    {8, 11, 16, 8, "zsort 8-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
-    {11, 11, 8, 8, "zsort 11-bit, pixel sort 11-bit, 2048-key tiles, 8x8 wave tiles"},
-    {11, 11, 16, 16, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 16x4 wave tiles"},
-    {11, 11, 16, 4, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, 4x16 wave tiles"},
-    {10, 11, 16, 8, "zsort 10-bit, pixel sort 11-bit, 4096-key tiles, 8x8 wave tiles"},
-    {8, 8, 8, 8, "zsort 8-bit, pixel sort 8-bit, 2048-key tiles, 8x8 wave tiles"},
+    {8, 8, 16, 2, "zsort 8-bit digits, pixel sort 8-bit digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {8, 8, 16, 0, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 1 lane/pixel 8x8"},
+    {8, 8, 16, 1, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 2 lanes/pixel 8x4"},
+    {8, 8, 16, 3, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {8, 8, 16, 4, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
+    {8, 11, 16, 2, "zsort 8-bit, pixel sort 11-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {11, 11, 16, 2, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {8, 8, 8, 2, "zsort 8-bit, pixel sort 8-bit, 2048-key tiles, blend 4 lanes/pixel 4x4"},
 };
 constexpr int kNumTunings = (int)(sizeof(kTunings) / sizeof(kTunings[0]));
-constexpr int kDefaultTuning = 0;
+constexpr int kDefaultTuning = 4;
 
 int tuning_count() { return kNumTunings; }
 const Tuning& tuning(int id) { return kTunings[id]; }
@@ -72,10 +72,10 @@ static int check_camera(const inpc_camera_t& c) {
     return INPC_OK;
 }
 
-// Builds the problem description from a host view table; wave_x of the
-// blend decides the tile grid, so it is part of the problem.
+// Builds the problem description from a host view table; the blend shape
+// decides the tile grid, so it is part of the problem.
 static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points, int F, int fdt,
-                        int mode, int wave_x, Problem& pb) {
+                        int mode, int shape, Problem& pb) {
     if (!views || n_views < 1 || n_points < 0) return INPC_EINVAL;
     if (n_views > 65536) return INPC_EUNSUPPORTED;
     if (F < 1 || F > 64) return INPC_EUNSUPPORTED;
@@ -86,7 +86,7 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
     pb.F = F;
     pb.fdt = fdt;
     pb.mode = mode;
-    const int bw = blend_block_w(wave_x), bh = blend_block_h(wave_x);
+    const int bw = blend_block_w(shape), bh = blend_block_h(shape);
     int64_t vp = 0, pix = 0, tiles = 0;
     for (int v = 0; v < n_views; ++v) {
         const inpc_view_t& in = views[v];
@@ -361,7 +361,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
     build_fragments(pb, tn, xyz, opacity, frag_base, fo, ws, L.fwd_build, m_dev, s);
     ProfScope p(kStBlendFwd, s);
-    launch_blend_fwd(pb.F, pb.fdt, tn.blend_wave_x, at<GpuView>(ws, L.fwd_build.views),
+    launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
                      (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
                      at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
                      image, t_final, at<PixelState>(saved, L.s_state),
@@ -370,7 +370,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
 }
 
 // ------------------------------------------------------------ backward
-static int backward(const Problem& pb, int tid, const float* xyz, const void* feat,
+static int backward(const Problem& pb, int tid, float tau, const float* xyz, const void* feat,
                     const float* opacity, const void* saved, size_t saved_bytes,
                     const float* g_img, const float* g_t, float* grad_feat, float* grad_opa,
                     void* ws, size_t ws_bytes, hipStream_t s) {
@@ -402,10 +402,10 @@ static int backward(const Problem& pb, int tid, const float* xyz, const void* fe
     }
     {
     ProfScope p(kStBlendBwd, s);
-    launch_blend_bwd(pb.F, pb.fdt, tn.blend_wave_x, views, (int)pb.views.size(), pb.n_tiles,
+    launch_blend_bwd(pb.F, pb.fdt, tn.blend_shape, views, (int)pb.views.size(), pb.n_tiles,
                      at<const uint2>(const_cast<void*>(frag_base), fo->range),
                      at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
-                     at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat,
+                     at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
                      at<const PixelState>(sv, L.s_state), g_img, g_t,
                      at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
                      frec, s);
@@ -447,13 +447,13 @@ static inpc_view_t single_view(const inpc_camera_t* cam, int64_t n_points) {
     return v;
 }
 
-static int wave_x_of(int tid) { return kTunings[tid].blend_wave_x; }
+static int shape_of(int tid) { return kTunings[tid].blend_shape; }
 
 // Problem for sizing: tile counts do not enter any buffer size.
 static int sizes_impl(const inpc_view_t* views, int n_views, int64_t n_points, int F, int fdt,
                       int mode, size_t* fwd_ws, size_t* saved, size_t* bwd_ws) {
     Problem pb;
-    const int rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    const int rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb);
     if (rc) return rc;
     const Layout L = make_layout(pb);
     if (fwd_ws) *fwd_ws = L.fwd_bytes;
@@ -471,11 +471,11 @@ static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     int rc = check_settings(st, &treq, &tau, &mode);
     if (rc) return rc;
     Problem pb;
-    rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb);
     if (rc) return rc;
     const int tid = resolve_tuning(treq, pb);
-    if (wave_x_of(tid) != 8) {
-        rc = make_problem(views, n_views, n_points, F, fdt, mode, wave_x_of(tid), pb);
+    if (shape_of(tid) != 0) {
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb);
         if (rc) return rc;
     }
     rc = check_arrays(pb, xyz, feat, opa);
@@ -495,11 +495,11 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     int rc = check_settings(st, &treq, &tau, &mode);
     if (rc) return rc;
     Problem pb;
-    rc = make_problem(views, n_views, n_points, F, fdt, mode, 8, pb);
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb);
     if (rc) return rc;
     const int tid = resolve_tuning(treq, pb);
-    if (wave_x_of(tid) != 8) {
-        rc = make_problem(views, n_views, n_points, F, fdt, mode, wave_x_of(tid), pb);
+    if (shape_of(tid) != 0) {
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb);
         if (rc) return rc;
     }
     rc = check_arrays(pb, xyz, feat, opa);
@@ -508,7 +508,7 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     if (pb.n_vp > 0 && (!grad_feat || !grad_opa || !aligned(grad_feat, 16) || !aligned(grad_opa, 4)))
         return INPC_EINVAL;
     if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
-    return backward(pb, tid, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa, ws,
+    return backward(pb, tid, tau, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa, ws,
                     ws_bytes, static_cast<hipStream_t>(stream));
 }
 
@@ -590,7 +590,7 @@ int inpc_sum_view_grads(const inpc_view_t* views, int32_t n_views, int64_t n_poi
                         const float* vg_feat, const float* vg_opa, float* g_feat, float* g_opa,
                         void* ws, size_t ws_bytes, void* stream) {
     Problem pb;
-    int rc = make_problem(views, n_views, n_points, F, INPC_F32, INPC_SAVE, 8, pb);
+    int rc = make_problem(views, n_views, n_points, F, INPC_F32, INPC_SAVE, 0, pb);
     if (rc) return rc;
     if (n_points > 0 && (!g_feat || !g_opa || !aligned(g_feat, 16))) return INPC_EINVAL;
     if (pb.n_vp > 0 && (!vg_feat || !vg_opa || !aligned(vg_feat, 16))) return INPC_EINVAL;
@@ -614,7 +614,7 @@ const char* inpc_tuning_name(int32_t id) {
 int inpc_tuning_for(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
                     int32_t fdt) {
     Problem pb;
-    const int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    const int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 0, pb);
     if (rc) return rc;
     return resolve_tuning(-1, pb);
 }
@@ -625,7 +625,7 @@ int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_po
                          size_t fwd_ws_bytes, uint64_t* keys_host, uint32_t* ids_host, int64_t cap,
                          int64_t* m_out, uint32_t* n_blended_host, void* stream) {
     Problem pb;
-    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 0, pb);
     if (rc) return rc;
     if (!saved || !m_out) return INPC_EINVAL;
     const Layout L = make_layout(pb);
@@ -728,7 +728,7 @@ int inpc_autotune(const float* xyz, const void* feat, int32_t fdt, const float* 
                   const char* cache_path, float* best_ms, void* stream) {
     if (repeats < 1) repeats = 1;
     Problem pb;
-    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 8, pb);
+    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 0, pb);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;

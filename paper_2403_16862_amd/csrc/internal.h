@@ -15,7 +15,7 @@ struct Tuning {
     int zdigit;       // digit bits of the per-point depth sort
     int pdigit;       // digit bits of the per-fragment pixel sort
     int sort_items;   // keys per thread in a sort tile (tile = 256 * items)
-    int blend_wave_x; // blend: pixels per wave along x (wave covers wave_x * (64/wave_x))
+    int blend_shape;  // blend: lanes per pixel and wave tile, see blend_shape_dims()
     const char* name;
 };
 
@@ -81,14 +81,14 @@ struct alignas(16) PixelState {
     uint32_t pad0, pad1, pad2;
 };
 
-void launch_blend_fwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
+void launch_blend_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
                       float* t_before, hipStream_t s);
 
-void launch_blend_bwd(int F, int feat_dtype, int wave_x, const GpuView* views, int n_views,
+void launch_blend_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
-                      const void* feat, const PixelState* state, const float* g_img,
+                      const void* feat, float tau, const PixelState* state, const float* g_img,
                       const float* g_t, float* t_before, int rebuild_t, float2* frec, hipStream_t s);
 
 void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
@@ -99,9 +99,25 @@ void launch_sum_view_grads(const GpuView* views, int n_views, int64_t n_points, 
                            const float* vg_feat, const float* vg_opa, float* g_feat, float* g_opa,
                            hipStream_t s);
 
-// Tile geometry of the blend: a block of 4 waves covers a 2x2 arrangement of
-// wave tiles; a wave tile is wave_x pixels wide and 64/wave_x tall.
-inline int blend_block_w(int wave_x) { return 2 * wave_x; }
-inline int blend_block_h(int wave_x) { return 2 * (64 / wave_x); }
+// Blend shapes (must match dispatch_shape in blend_common.h): lanes per
+// pixel L and wave-tile width WXP; a wave covers WXP x (64/L/WXP) pixels and
+// a block of 4 waves a 2x2 arrangement of wave tiles.
+struct BlendShape {
+    int lanes, wxp;
+};
+inline BlendShape blend_shape_dims(int shape) {
+    switch (shape) {
+        case 1: return {2, 8};
+        case 2: return {4, 4};
+        case 3: return {8, 4};
+        case 4: return {16, 2};
+        default: return {1, 8};
+    }
+}
+inline int blend_block_w(int shape) { return 2 * blend_shape_dims(shape).wxp; }
+inline int blend_block_h(int shape) {
+    const BlendShape b = blend_shape_dims(shape);
+    return 2 * (64 / b.lanes / b.wxp);
+}
 
 }  // namespace inpc

@@ -41,26 +41,42 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __
                                                               uint32_t n_bound, int shift,
                                                               uint32_t* __restrict__ counts,
                                                               uint32_t stride) {
+    // One LDS histogram per wave.  A row whose lanes all carry the same digit
+    // (common once the lower digits are sorted) costs a single update; other
+    // rows use per-lane LDS atomics.
     constexpr int BINS = 1 << D;
     constexpr int TILE = kSortBlock * ITEMS;
-    __shared__ uint32_t s_hist[BINS];
+    constexpr int WAVES = kSortBlock / kWave;
+    __shared__ uint32_t s_hist[WAVES][BINS];
     const uint32_t n = live_count(n_dev, n_bound);
     const uint32_t tile = blockIdx.x;
     if ((uint64_t)tile * TILE >= n) return;
-    for (int i = threadIdx.x; i < BINS; i += kSortBlock) s_hist[i] = 0;
+    for (int i = threadIdx.x; i < WAVES * BINS; i += kSortBlock) (&s_hist[0][0])[i] = 0;
     __syncthreads();
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t base = tile * TILE + w * (ITEMS * kWave);
+    uint32_t* h = s_hist[w];
 #pragma unroll 4
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
         const bool valid = idx < n;
         const uint32_t d = valid ? (keys[idx] >> shift) & (BINS - 1) : 0u;
-        const uint64_t peers = match_digit<D>(d, valid);
-        if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_hist[d], (uint32_t)__popcll(peers));
+        const uint64_t act = __ballot(valid);
+        const uint32_t d0 = __shfl(d, 0);
+        const uint64_t same = __ballot(valid && d == d0);
+        if (same == act && (act & 1ull)) {
+            if (lane == 0) h[d0] += (uint32_t)__popcll(act);
+        } else if (valid) {
+            atomicAdd(&h[d], 1u);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < BINS; i += kSortBlock) counts[(size_t)i * stride + tile] = s_hist[i];
+    for (int i = threadIdx.x; i < BINS; i += kSortBlock) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) c += s_hist[ww][i];
+        counts[(size_t)i * stride + tile] = c;
+    }
 }
 
 // Row-wise exclusive scan of counts[bin][0..tiles) in place; bin totals out.

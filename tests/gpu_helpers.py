@@ -121,6 +121,9 @@ def grad_err(gpu: np.ndarray, ref: np.ndarray):
 
 
 def check_grads(gf, go, ref, tol=GRAD_TOL):
+    if ref["grad_opa"].size == 0:
+        assert gf.size == 0 and go.size == 0
+        return
     ef = grad_err(gf, ref["grad_feat"])
     eo = grad_err(go, ref["grad_opa"])
     say(f"    grad_feat err max {ef.max():.3e} p99 {np.quantile(ef, 0.99):.3e}; "
