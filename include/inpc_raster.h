@@ -161,7 +161,7 @@ int inpc_rasterize_bwd_batched(const float *xyz, const void *feat, int32_t feat_
 
 /* grad_feat[p] = sum over views v containing p, in view order, of the view
  * point rows of p (and likewise grad_opacity).  Points no view contains get
- * zeros.  Deterministic.  ws: at least 128 * n_views bytes of device scratch. */
+ * zeros.  Deterministic.  ws: at least 256 * n_views bytes of device scratch. */
 int inpc_sum_view_grads(const inpc_view_t *views_host, int32_t n_views, int64_t n_points,
                         int32_t F, const float *view_grad_feat, const float *view_grad_opacity,
                         float *grad_feat, float *grad_opacity, void *ws, size_t ws_bytes,

@@ -352,7 +352,7 @@ def sum_view_grads(views, n_views: int, n_points: int, vg_feat, vg_opa):
     dev = vg_feat.device
     gf = torch.empty((n_points, F), dtype=torch.float32, device=dev)
     go = torch.empty((n_points,), dtype=torch.float32, device=dev)
-    ws = _buffer(128 * n_views, dev)
+    ws = _buffer(256 * n_views, dev)
     _check(lib().inpc_sum_view_grads(views, n_views, int(n_points), F, _ptr(vg_feat.contiguous()),
                                      _ptr(vg_opa.contiguous()), _ptr(gf), _ptr(go), _ptr(ws), ws.numel(),
                                      _stream()), "inpc_sum_view_grads")

@@ -595,7 +595,8 @@ int inpc_sum_view_grads(const inpc_view_t* views, int32_t n_views, int64_t n_poi
     if (n_points > 0 && (!g_feat || !g_opa || !aligned(g_feat, 16))) return INPC_EINVAL;
     if (pb.n_vp > 0 && (!vg_feat || !vg_opa || !aligned(vg_feat, 16))) return INPC_EINVAL;
     if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
-    if (ws_bytes < pb.views.size() * sizeof(GpuView)) return INPC_EWORKSPACE;
+    static_assert(sizeof(GpuView) <= 256, "view table entry");
+    if (ws_bytes < pb.views.size() * 256) return INPC_EWORKSPACE;
     if (n_points == 0) return INPC_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     GpuView* dv = static_cast<GpuView*>(ws);
