@@ -138,9 +138,11 @@ def main():
     tn = pr.tuning_table()
     tid = args.tuning if args.tuning >= 0 else pr.lib().inpc_tuning_for(
         pr.make_views([s.cam], [0], [s.n]), 1, s.n, s.F, 0)
-    zdig = 8 if tn[tid].startswith("zsort 8") else (10 if tn[tid].startswith("zsort 10") else 11)
-    pdig = 8 if "pixel sort 8" in tn[tid] else 11
-    zpasses = -(-32 // zdig)
+    import re
+    zdig = int(re.search(r"depth(?: sort)? (\d+)-bit", tn[tid]).group(1))
+    pdig = int(re.search(r"pixel(?: sort)? (\d+)-bit", tn[tid]).group(1))
+    zspan = int(np.float32(s.cam.far).view(np.uint32)) - int(np.float32(s.cam.near).view(np.uint32))
+    zpasses = -(-max(1, zspan.bit_length()) // zdig)
     pbits = max(1, (P - 1).bit_length())
     ppasses = -(-pbits // pdig)
     model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses)

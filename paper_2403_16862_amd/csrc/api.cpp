@@ -19,17 +19,19 @@ namespace inpc {
 
 // ------------------------------------------------------------ tuning table
 static const Tuning kTunings[] = {
-    {8, 8, 16, 2, "zsort 8-bit digits, pixel sort 8-bit digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {8, 8, 16, 0, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 1 lane/pixel 8x8"},
-    {8, 8, 16, 1, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 2 lanes/pixel 8x4"},
-    {8, 8, 16, 3, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {8, 8, 16, 4, "zsort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
-    {8, 11, 16, 2, "zsort 8-bit, pixel sort 11-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {11, 11, 16, 2, "zsort 11-bit, pixel sort 11-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {8, 8, 8, 2, "zsort 8-bit, pixel sort 8-bit, 2048-key tiles, blend 4 lanes/pixel 4x4"},
+    {9, 7, 16, 3, "depth sort 9-bit digits, pixel sort 7-bit digits, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {8, 8, 16, 4, "depth 8-bit, pixel 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
+    {9, 8, 16, 4, "depth 9-bit, pixel 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
+    {9, 7, 32, 3, "depth 9-bit, pixel 7-bit, 8192-key tiles, blend 8 lanes/pixel 4x2"},
+    {9, 7, 16, 4, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
+    {9, 11, 16, 3, "depth 9-bit, pixel 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {9, 7, 16, 2, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {9, 7, 16, 1, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 2 lanes/pixel 8x4"},
+    {9, 7, 16, 0, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 1 lane/pixel 8x8"},
+    {10, 11, 16, 3, "depth 10-bit, pixel 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
 };
 constexpr int kNumTunings = (int)(sizeof(kTunings) / sizeof(kTunings[0]));
-constexpr int kDefaultTuning = 4;
+constexpr int kDefaultTuning = 0;
 
 int tuning_count() { return kNumTunings; }
 const Tuning& tuning(int id) { return kTunings[id]; }
@@ -57,6 +59,9 @@ struct Problem {
     int64_t n_tiles = 0;    // blend tiles
     int F = 0, fdt = 0, mode = 0;
     int pixel_bits = 0;
+    uint32_t zbase = 0;      // depth key = float bits of z - zbase
+    uint32_t zkey_none = 0;  // depth key of points without splats (> every real key)
+    int zbits = 32;          // key bits of the depth sort
 };
 
 static bool finite_f(float x) { return std::isfinite(x); }
@@ -123,6 +128,21 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
     int bits = 0;
     while (bits < 32 && (((int64_t)1 << bits) < pix)) ++bits;
     pb.pixel_bits = bits;
+    // Depth keys: z lies strictly between a view's near and far planes, both
+    // non-negative, where float bit patterns are monotone.
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+    for (int v = 0; v < n_views; ++v) {
+        uint32_t bn, bf;
+        std::memcpy(&bn, &views[v].cam.near_plane, 4);
+        std::memcpy(&bf, &views[v].cam.far_plane, 4);
+        lo = std::min(lo, bn);
+        hi = std::max(hi, bf);
+    }
+    pb.zbase = lo;
+    pb.zkey_none = hi - lo;   // real keys are < bits(far) - zbase
+    bits = 1;
+    while (bits < 32 && (((uint64_t)1 << bits) <= pb.zkey_none)) ++bits;
+    pb.zbits = bits;
     return INPC_OK;
 }
 
@@ -307,7 +327,7 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* zv_in = at<uint32_t>(build_base, bo.zv_in);
     {
         ProfScope p(kStProject, s);
-        launch_project(xyz, opacity, views, nv, pb.n_vp, rec, zk_in, zv_in, s);
+        launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in, s);
     }
     uint32_t* zk_a = at<uint32_t>(build_base, bo.zk_a);
     uint32_t* zv_a = at<uint32_t>(build_base, bo.zv_a);
@@ -316,10 +336,10 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* counts = at<uint32_t>(build_base, bo.counts);
     {
         ProfScope p(kStDepthSort, s);
-        launch_radix_sort(tn.zdigit, tn.sort_items, 32, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
+        launch_radix_sort(tn.zdigit, tn.sort_items, pb.zbits, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
                           pb.n_vp, counts, s);
     }
-    const int zp = radix_passes(tn.zdigit, 32);
+    const int zp = radix_passes(tn.zdigit, pb.zbits);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
 
     // Pixel sort: emission writes (kb, vb); the sorted ids must end in the
@@ -667,7 +687,7 @@ int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_po
     for (int64_t q = 0; q < pb.n_pixels; ++q) {
         for (uint32_t i = range[q].x; i < range[q].y && i < m; ++i) {
             const uint32_t vp = ids_host[i] >> 2;
-            const uint32_t zb = vp < zk.size() ? zk[vp] : 0xFFFFFFFFu;
+            const uint32_t zb = vp < zk.size() ? zk[vp] + pb.zbase : 0xFFFFFFFFu;
             keys_host[i] = ((uint64_t)q << 32) | zb;
         }
     }

@@ -47,7 +47,8 @@ void launch_upload_views(const GpuView* host_views, int n, GpuView* dev, hipStre
 void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
-                    int64_t n_vp, PointRec* rec, uint32_t* zkey, uint32_t* zval, hipStream_t s);
+                    int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
+                    uint32_t* zval, hipStream_t s);
 
 // Emission of the fragments of depth-sorted view points (count, scan, write).
 constexpr int kEmitBlock = 256;

@@ -87,10 +87,15 @@ __device__ __forceinline__ void project_point(const GpuView& V, float x, float y
     zbits = __float_as_uint(zc);
 }
 
+// Depth keys are float32 bits of z minus the bits of the smallest near
+// plane (z > near >= 0 and bits are monotone there), so they need only as
+// many bits as the (near, far) range spans; points without splats get
+// zkey_none, which is larger than every real key.
 __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
                                                  const float* __restrict__ opacity,
                                                  const GpuView* __restrict__ views, int n_views,
-                                                 int64_t n_vp, PointRec* __restrict__ rec,
+                                                 int64_t n_vp, uint32_t zbase, uint32_t zkey_none,
+                                                 PointRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey,
                                                  uint32_t* __restrict__ zval) {
     const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,16 +111,17 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
     project_point(V, x, y, z, r, zb);
     r.opa = opacity[p];
     rec[vp] = r;
-    zkey[vp] = zb;
+    zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
     zval[vp] = (uint32_t)vp | (anc_mask(r.anc) << 28);
 }
 
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
-                    int64_t n_vp, PointRec* rec, uint32_t* zkey, uint32_t* zval, hipStream_t s) {
+                    int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
+                    uint32_t* zval, hipStream_t s) {
     if (n_vp == 0) return;
     const int64_t blocks = (n_vp + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, xyz, opa, views, n_views,
-                       n_vp, rec, zkey, zval);
+                       n_vp, zbase, zkey_none, rec, zkey, zval);
 }
 
 // ----------------------------------------------------------------- emission

@@ -108,26 +108,12 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_rows(uint32_t* __restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = running;
 }
 
-// Exclusive scan of the bin totals (<= 4096 bins) in one block.
-__global__ __launch_bounds__(1024) void k_scan_bins(uint32_t* __restrict__ totals, int bins) {
-    __shared__ uint32_t s_tmp[1024 / kWave];
-    uint32_t running = 0;
-    for (int base = 0; base < bins; base += 1024) {
-        const int i = base + threadIdx.x;
-        const uint32_t x = i < bins ? totals[i] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_excl_sum<1024>(x, total, s_tmp);
-        if (i < bins) totals[i] = running + ex;
-        running += total;
-    }
-}
-
 template <int D, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev,
     uint32_t n_bound, int shift, const uint32_t* __restrict__ row_prefix, uint32_t stride,
-    const uint32_t* __restrict__ bin_base) {
+    const uint32_t* __restrict__ bin_total) {
     constexpr int BINS = 1 << D;
     constexpr int WAVES = kSortBlock / kWave;
     constexpr int TILE = kSortBlock * ITEMS;
@@ -188,20 +174,24 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         }
         my_tot[j] = sum;
     }
-    // Exclusive scan of digit totals over the block (digits are owned
-    // thread-major: thread t owns digits t, t+256, ...; scan in digit order).
+    // Exclusive scans over digits (digits are owned thread-major: thread t
+    // owns digits t, t+256, ...): of this tile's digit totals (LDS slots) and
+    // of the global digit totals of the pass (where each digit starts).
     {
-        uint32_t running = 0;
+        uint32_t running = 0, running_g = 0;
 #pragma unroll
         for (int j = 0; j < (BINS + kSortBlock - 1) / kSortBlock; ++j) {
-            uint32_t total;
-            const uint32_t ex = block_excl_sum<kSortBlock>(my_tot[j], total, s_tmp);
             const int d = threadIdx.x + j * kSortBlock;
+            uint32_t total, total_g;
+            const uint32_t ex = block_excl_sum<kSortBlock>(my_tot[j], total, s_tmp);
+            const uint32_t gtot = d < BINS ? bin_total[d] : 0u;
+            const uint32_t exg = block_excl_sum<kSortBlock>(gtot, total_g, s_tmp);
             if (d < BINS) {
                 s_start[d] = running + ex;
-                s_dst[d] = bin_base[d] + row_prefix[(size_t)d * stride + tile];
+                s_dst[d] = running_g + exg + row_prefix[(size_t)d * stride + tile];
             }
             running += total;
+            running_g += total_g;
         }
     }
     __syncthreads();
@@ -242,7 +232,6 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
         ProfScope p(kStSortScan, s);
         hipLaunchKernelGGL(k_scan_rows, dim3(1u << D), dim3(kSortBlock), 0, s, counts, stride, n_dev,
                            (uint32_t)n_bound, (uint32_t)(kSortBlock * ITEMS), totals);
-        hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, s, totals, 1 << D);
     }
     {
         ProfScope p(kStSortDownsweep, s);
@@ -257,8 +246,10 @@ using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, 
 static PassFn pass_fn(int digit, int items) {
 #define INPC_CASE(D, I) \
     if (digit == D && items == I) return &sort_pass<D, I>;
-    INPC_CASE(8, 8) INPC_CASE(8, 16)
-    INPC_CASE(10, 8) INPC_CASE(10, 16)
+    INPC_CASE(7, 16) INPC_CASE(7, 32)
+    INPC_CASE(8, 8) INPC_CASE(8, 16) INPC_CASE(8, 32)
+    INPC_CASE(9, 16) INPC_CASE(9, 32)
+    INPC_CASE(10, 16)
     INPC_CASE(11, 8) INPC_CASE(11, 16)
 #undef INPC_CASE
     return nullptr;
