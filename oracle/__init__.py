@@ -6,9 +6,12 @@ binding) never imports or calls it.
 
 Functions follow the paper's steps: ``fragments`` (projection, Eq. 5, and
 bilinear splatting, Eq. 6, then per-pixel depth order), ``blend_forward``
-(Eq. 1 with early termination, Appendix A.6) and ``blend_backward`` (its
+(Eq. 1 with early termination, Appendix A.6), ``blend_backward`` (its
 exact derivative with the termination count held fixed, per-point
-bilinear-weighted combination, Appendix A.6).
+bilinear-weighted combination, Appendix A.6), ``blend_weight`` (the per-point
+blend weight for the probability updates, combined with the bilinear
+weights, Appendix A.6) and ``multisample`` (per-pixel average over several
+sampled clouds, Section 3.2).
 """
 
 from __future__ import annotations
@@ -52,6 +55,8 @@ def lib():
         L.orc_blend_fwd.argtypes = [i64, P, P, P, P, P, ctypes.c_int, i32, dbl, P, P, P, P, P]
         L.orc_blend_bwd.restype = ctypes.c_int
         L.orc_blend_bwd.argtypes = [i64, P, P, P, P, P, ctypes.c_int, i32, P, P, P, i64, P, P]
+        L.orc_blend_weight.restype = None
+        L.orc_blend_weight.argtypes = [i64, P, P, P, P, P, i64, P]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
         _lib = L
@@ -181,6 +186,36 @@ def blend_backward(lists: Lists, opa: np.ndarray, feat: np.ndarray, n_blended: n
     if rc != 0:
         raise RuntimeError("orc_blend_bwd failed")
     return dict(grad_feat=gf, grad_opa=go)
+
+
+def blend_weight(lists: Lists, opa: np.ndarray, n_blended: np.ndarray) -> np.ndarray:
+    """Per-point blend weight b_p = sum_k w_k T_k alpha_k over the point's blended splats."""
+    opa = np.ascontiguousarray(opa, np.float32)
+    nb = np.ascontiguousarray(n_blended, np.int32)
+    out = np.empty(opa.shape[0], np.float64)
+    lib().orc_blend_weight(lists.P, _ptr(lists.start), _ptr(lists.ids), _ptr(lists.w), _ptr(opa), _ptr(nb),
+                           opa.shape[0], _ptr(out))
+    return out
+
+
+def multisample(xyz, feat, opa, cam, offsets, counts, tau: float = 1e-4, want_samples: bool = False):
+    """Multisampled inference (Section 3.2): cloud k = points [offsets[k], +counts[k])
+    rendered for ``cam`` with Eq. 1, then per-pixel means of the K images and of
+    the K final transmittances (FP64).  Returns dict(image [P,F], t_final [P][, samples])."""
+    samples = []
+    for o, c in zip(offsets, counts):
+        sl = slice(int(o), int(o) + int(c))
+        lists = fragments(np.ascontiguousarray(xyz[sl]), cam)
+        r = blend_forward(lists, opa[sl], feat[sl], tau, want_t_after=want_samples)
+        r["lists"] = lists
+        samples.append(r)
+    K = len(samples)
+    image = sum(s["image"] for s in samples) / K
+    t_final = sum(s["t_final"] for s in samples) / K
+    out = dict(image=image, t_final=t_final)
+    if want_samples:
+        out["samples"] = samples
+    return out
 
 
 def render(xyz, feat, opa, cam, tau: float = 1e-4):

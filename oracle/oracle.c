@@ -323,6 +323,30 @@ out:
     return rc;
 }
 
+/*
+ * Per-point blend weight for the probability-field updates (Section 3.1,
+ * Eq. 2 and Eq. 3 use the transmitted blending weight b = alpha T of Eq. 1;
+ * Appendix A.6 combines a point's per-splat weights in a sum weighted by the
+ * bilinear weights).  With the termination count n_blended[q] of each pixel:
+ *   b[p] = sum over the blended splats k of p of  w_k * T_k * alpha_k.
+ * Points without blended splats get 0.
+ */
+void orc_blend_weight(int64_t P, const int64_t *start, const uint32_t *s_id, const double *s_w,
+                      const float *opa, const int32_t *n_blended, int64_t N, double *bw) {
+    for (int64_t p = 0; p < N; ++p) bw[p] = 0.0;
+    /* serial over pixels: several pixels add into one point */
+    for (int64_t q = 0; q < P; ++q) {
+        double T = 1.0;
+        for (int32_t k = 0; k < n_blended[q]; ++k) {
+            int64_t i = start[q] + k;
+            int64_t p = s_id[i] >> 2;
+            double alpha = (double)opa[p] * s_w[i];
+            bw[p] += s_w[i] * (T * alpha);
+            T = T * (1.0 - alpha);
+        }
+    }
+}
+
 /* Number of OpenMP threads a parallel region of this library uses. */
 int orc_num_threads(void) {
 #ifdef _OPENMP

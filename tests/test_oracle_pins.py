@@ -412,3 +412,202 @@ def test_unsplatted_points_get_exact_zero_gradient():
     rng = np.random.default_rng(0)
     gb = oracle.blend_backward(L, opa, feat, o["n_blended"], rng.normal(size=(L.P, 3)).astype(np.float32))
     assert np.all(gb["grad_feat"][:7] == 0) and np.all(gb["grad_opa"][:7] == 0)
+
+
+# ------------------------------------------------ per-point blend weight
+def test_blend_weight_single_and_stacked_splats():
+    # points on a pixel centre have one splat of weight 1, so b = T alpha
+    af, ab = 0.375, 0.625
+    xyz, feat, opa, cam = _stack((3, 4), [3.0, 1.5], [ab, af], [[1.0], [1.0]])
+    L = oracle.fragments(xyz, cam)
+    o = oracle.blend_forward(L, opa, feat, 1e-4)
+    b = oracle.blend_weight(L, opa, o["n_blended"])
+    assert b[1] == af and b[0] == (1 - af) * ab
+
+
+def test_blend_weight_bilinear_weighted_closed_form():
+    # a lone point at u = 5.75, v = 3.25 (weights 0.1875, 0.0625, 0.5625, 0.1875)
+    # is the only splat of its four pixels: b = a * sum_c w_c^2
+    xyz = np.asarray([[5.75, 3.25, 1.0]], np.float32)
+    cam = ident_cam(16, 16)
+    L = oracle.fragments(xyz, cam)
+    a = np.float32(0.5)
+    o = oracle.blend_forward(L, np.asarray([a]), np.ones((1, 1), np.float32), 1e-4)
+    b = oracle.blend_weight(L, np.asarray([a]), o["n_blended"])
+    w = np.asarray([0.1875, 0.0625, 0.5625, 0.1875])
+    assert b[0] == float(a) * float(np.sum(w * w))
+
+
+def test_blend_weight_sums_to_coverage_for_centre_points():
+    # with every splat at weight 1 the weighted sum is the plain sum, and the
+    # blend weights of a pixel add up to 1 - T_final (partition of unity)
+    rng = np.random.default_rng(8)
+    W = H = 12
+    n = 600
+    x = rng.integers(0, W, n) + 0.5
+    y = rng.integers(0, H, n) + 0.5
+    z = 2.0 ** rng.integers(0, 5, n)              # powers of two: x*z/z is exact in float32
+    xyz = np.stack([x * z, y * z, z], 1).astype(np.float32)
+    cam = ident_cam(W, H)
+    L = oracle.fragments(xyz, cam)
+    assert np.all(L.w == 1.0)
+    opa = rng.uniform(0.05, 0.95, n).astype(np.float32)
+    o = oracle.blend_forward(L, opa, np.ones((n, 1), np.float32), 1e-4)
+    b = oracle.blend_weight(L, opa, o["n_blended"])
+    assert np.sum(b) == pytest.approx(np.sum(1.0 - o["t_final"]), rel=1e-12)
+
+
+# ------------------------------------------------------------- multisampling
+def test_multisample_single_cloud_is_plain_render():
+    s = workloads.config1()
+    ms = oracle.multisample(s.xyz, s.feat, s.opa, s.cam, [0], [s.n])
+    ref = oracle.blend_forward(oracle.fragments(s.xyz, s.cam), s.opa, s.feat, 1e-4)
+    assert np.array_equal(ms["image"], ref["image"]) and np.array_equal(ms["t_final"], ref["t_final"])
+
+
+def test_multisample_two_opaque_clouds_average_not_union():
+    # cloud 0: an opaque white point in front; cloud 1: an opaque black point
+    # behind it on the same pixel centre.  Each cloud alone covers the pixel,
+    # so the mean is 1/2 with T = 0; rendering the union would give 1.
+    xyz, feat, opa, cam = _stack((2, 5), [1.0, 2.0], [1.0, 1.0], [[1.0], [0.0]])
+    ms = oracle.multisample(xyz, feat, opa, cam, [0, 1], [1, 1])
+    q = 5 * 8 + 2
+    assert ms["image"][q, 0] == 0.5 and ms["t_final"][q] == 0.0
+    other = np.arange(64) != q
+    assert np.all(ms["image"][other] == 0) and np.all(ms["t_final"][other] == 1.0)
+    union = oracle.blend_forward(oracle.fragments(xyz, cam), opa, feat, 1e-4)
+    assert union["image"][q, 0] == 1.0
+
+
+def test_multisample_closed_form_and_cloud_order():
+    a1, a2 = 0.25, 0.75
+    c1, c2 = [0.5, 1.0], [1.0, 0.25]
+    xyz, feat, opa, cam = _stack((0, 0), [3.0, 1.5], [a1, a2], [c1, c2])
+    ms = oracle.multisample(xyz, feat, opa, cam, [0, 1], [1, 1])
+    assert np.array_equal(ms["image"][0], [(a1 * c1[0] + a2 * c2[0]) / 2, (a1 * c1[1] + a2 * c2[1]) / 2])
+    assert ms["t_final"][0] == ((1 - a1) + (1 - a2)) / 2
+    swapped = oracle.multisample(xyz, feat, opa, cam, [1, 0], [1, 1])
+    assert np.array_equal(ms["image"], swapped["image"])
+
+
+def test_multisample_overlapping_clouds_and_repeats():
+    # K copies of one cloud average to that cloud's image (up to the rounding
+    # of the mean: K * x / K is exact for K a power of two)
+    s = workloads.config1()
+    one = oracle.multisample(s.xyz, s.feat, s.opa, s.cam, [0], [s.n])
+    four = oracle.multisample(s.xyz, s.feat, s.opa, s.cam, [0] * 4, [s.n] * 4)
+    assert np.array_equal(one["image"], four["image"]) and np.array_equal(one["t_final"], four["t_final"])
+
+
+# --------------------------------------------------- appearance (Section 3.3)
+from oracle import appearance as A   # noqa: E402
+
+
+def _unit(rng, n):
+    d = rng.normal(size=(n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_sh_basis_matches_complex_harmonics_from_scipy():
+    # real SH from scipy's complex SH (Condon-Shortley phase included):
+    # sqrt(2) Re Y_l^m for m > 0, Y_l^0, sqrt(2) Im Y_l^|m| for m < 0
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(11)
+    d = _unit(rng, 500)
+    theta = np.arccos(np.clip(d[:, 2], -1, 1))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    cols = []
+    for l in range(3):
+        for m in range(-l, l + 1):
+            Y = sph_harm_y(l, abs(m), theta, phi)
+            cols.append(np.sqrt(2) * Y.real if m > 0 else (Y.real if m == 0 else np.sqrt(2) * Y.imag))
+    ref = np.stack(cols, 1)
+    assert np.allclose(A.sh_basis(d), ref, atol=1e-13, rtol=0)
+
+
+def test_sh_basis_orthonormal_on_the_sphere():
+    # Gauss-Legendre in cos(theta) x uniform phi integrates these degree <= 4
+    # products exactly
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    phi = np.arange(16) * (2 * np.pi / 16)
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    w = np.meshgrid(wg, np.full(16, 2 * np.pi / 16), indexing="ij")
+    w = (w[0] * w[1]).reshape(-1)
+    st = np.sqrt(1 - ct ** 2)
+    d = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    Y = A.sh_basis(d)
+    G = (Y * w[:, None]).T @ Y
+    assert np.allclose(G, np.eye(9), atol=1e-13)
+
+
+def test_sh_addition_theorem_per_band():
+    rng = np.random.default_rng(12)
+    Y = A.sh_basis(_unit(rng, 100))
+    for l, sl in ((0, slice(0, 1)), (1, slice(1, 4)), (2, slice(4, 9))):
+        assert np.allclose(np.sum(Y[:, sl] ** 2, 1), (2 * l + 1) / (4 * np.pi), atol=1e-14)
+
+
+def test_opacity_activation_values_and_slope():
+    x = np.array([-40.0, -5.0, np.log(np.log(2.0)), 0.0, 3.0, 40.0])
+    a = A.opacity(x)
+    assert a[3] == pytest.approx(1 - np.exp(-1), rel=1e-15)
+    assert a[2] == pytest.approx(0.5, rel=1e-15)          # exp(x) = ln 2 gives exactly one half
+    assert a[0] == pytest.approx(np.exp(-40.0), rel=1e-15)  # tiny opacities keep full precision
+    assert a[5] == 1.0 and np.all(np.diff(a) > 0) and np.all((a >= 0) & (a <= 1))
+    h = 1e-6
+    fd = (A.opacity(x[1:5] + h) - A.opacity(x[1:5] - h)) / (2 * h)
+    assert np.allclose(A.opacity_grad(x[1:5]), fd, rtol=1e-8)
+
+
+def test_appearance_constant_band_and_direction_convention():
+    # only the l = 0 coefficients set: the feature is view-independent;
+    # only (1,0) set: the feature follows the z component of the direction
+    rng = np.random.default_rng(13)
+    cam = workloads.canonical_camera(64, 32)
+    xyz = (rng.normal(size=(50, 3)) + [0, 0, 5]).astype(np.float32)
+    raw = np.zeros((50, A.N_RAW), np.float32)
+    raw[:, 1:5] = [1.0, 2.0, -1.0, 0.5]
+    _, f = A.forward(xyz, raw, [cam], [0], [50])
+    assert np.allclose(f, np.array([1.0, 2.0, -1.0, 0.5]) * 0.5 / np.sqrt(np.pi), rtol=1e-15)
+    raw[:] = 0
+    raw[:, 1 + 4 * 2] = 1.0                       # basis (1,0), channel 0
+    _, f = A.forward(xyz, raw, [cam], [0], [50])
+    d = xyz.astype(np.float64) / np.linalg.norm(xyz.astype(np.float64), axis=1, keepdims=True)
+    assert np.allclose(f[:, 0], np.sqrt(3 / (4 * np.pi)) * d[:, 2], rtol=1e-14)
+    assert np.all(f[:, 1:] == 0)
+
+
+def test_appearance_backward_is_the_adjoint():
+    # <g, J dr> = <J^T g, dr> for random perturbations (J linear in the SH part)
+    rng = np.random.default_rng(14)
+    cams = [workloads.canonical_camera(64, 32),
+            workloads.look_at_camera([0.5, 0.0, -1.0], [0, 0, 5], [0, -1, 0], 64, 32)]
+    N = 40
+    xyz = (rng.normal(size=(N, 3)) + [0, 0, 5]).astype(np.float32)
+    raw = rng.normal(size=(N, A.N_RAW)).astype(np.float32)
+    offs, cnts = [0, 10], [30, 30]                 # the views overlap on points 10..29
+    go = rng.normal(size=60)
+    gf = rng.normal(size=(60, 4))
+    g = A.backward(xyz, raw, cams, offs, cnts, go, gf)
+    dr = np.zeros((N, A.N_RAW))
+    dr[:, 1:] = rng.normal(size=(N, 36)).astype(np.float32)   # the forward reads float32 values
+    o0, f0 = A.forward(xyz, raw, cams, offs, cnts)
+    # forward is linear in the coefficients: J dr = forward(dr) with zero opacity part
+    _, fd = A.forward(xyz, dr.astype(np.float64), cams, offs, cnts)
+    lhs = np.sum(gf * fd)
+    assert lhs == pytest.approx(np.sum(g[:, 1:] * dr[:, 1:]), rel=1e-12)
+    # opacity part by central differences
+    h = 1e-3
+    rp, rm = raw.astype(np.float64).copy(), raw.astype(np.float64).copy()
+    rp[:, 0] += h
+    rm[:, 0] -= h
+    op = np.concatenate([A.opacity(rp[o:o + c, 0]) for o, c in zip(offs, cnts)])
+    om = np.concatenate([A.opacity(rm[o:o + c, 0]) for o, c in zip(offs, cnts)])
+    fd_o = np.sum(go * (op - om)) / (2 * h)
+    assert fd_o == pytest.approx(np.sum(g[:, 0]), rel=1e-6)
+
+
+def test_camera_centre_is_the_look_at_eye():
+    eye = np.array([0.75, -0.25, -1.5])
+    cam = workloads.look_at_camera(eye, [0.0, 0.0, 5.0], [0.0, -1.0, 0.0], 64, 32)
+    assert np.allclose(A.camera_centre(cam), eye, atol=1e-6)

@@ -25,4 +25,8 @@ from .scenes import (  # noqa: F401
     config4,
     config5,
     cluster_points,
+    cluster_mixture,
+    sample_mixture,
+    multisample_clouds,
+    sh_raw,
 )

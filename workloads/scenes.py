@@ -134,6 +134,11 @@ def cluster_points(rng: np.random.Generator, n: int, n_clusters: int, cam0: Came
     its screen position uniform over the image; axis standard deviations are
     0.02*d*exp(U(-1.5,1.5)) along a random rotation.
     """
+    return sample_mixture(rng, cluster_mixture(rng, n_clusters, cam0), n)
+
+
+def cluster_mixture(rng: np.random.Generator, n_clusters: int, cam0: Camera):
+    """The cluster parameters of ``cluster_points`` (drawn first, in the same order)."""
     d = np.exp(rng.uniform(math.log(0.5), math.log(100.0), n_clusters))
     u = rng.uniform(0.0, cam0.width, n_clusters)
     v = rng.uniform(0.0, cam0.height, n_clusters)
@@ -147,6 +152,13 @@ def cluster_points(rng: np.random.Generator, n: int, n_clusters: int, cam0: Came
         np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], axis=1),
     ], axis=1)                                           # [K,3,3]
     sigma = 0.02 * d[:, None] * np.exp(rng.uniform(-1.5, 1.5, (n_clusters, 3)))
+    return centres, rot, sigma
+
+
+def sample_mixture(rng: np.random.Generator, mixture, n: int) -> np.ndarray:
+    """n points of a cluster mixture: a uniform cluster choice, then a Gaussian draw."""
+    centres, rot, sigma = mixture
+    n_clusters = centres.shape[0]
     k = rng.integers(0, n_clusters, n)
     nrm = rng.normal(size=(n, 3))
     local = nrm * sigma[k]
@@ -251,6 +263,35 @@ def config5(seed: int = 4, n: int = 32_000_000, n_poses: int = 8, far: float = F
         cams.append(c)
     return BatchedScene(_f32(xyz), _f32(feat), _f32(opa), cams, [0] * n_poses, [n] * n_poses,
                         name="config5")
+
+
+def multisample_clouds(seed: int = 6, n_per_cloud: int = 1_000_000, n_clouds: int = 4, width: int = 1280,
+                       height: int = 720, F: int = 4) -> BatchedScene:
+    """K point clouds drawn independently from one cluster mixture (256
+    clusters, as in the full-size scene) and seen by one look-at camera: the
+    inference-time multisampling of Section 3.2 (the paper uses 4 clouds and
+    4-D features).  Features U(0,1), opacity U(0.01,0.99)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cam0 = canonical_camera(width, height)
+    mix = cluster_mixture(rng, 256, cam0)
+    xyz = np.concatenate([sample_mixture(rng, mix, n_per_cloud) for _ in range(n_clouds)])
+    n = n_per_cloud * n_clouds
+    feat = rng.uniform(0.0, 1.0, (n, F))
+    opa = rng.uniform(0.01, 0.99, n)
+    cam = _random_look_at(rng, width, height)
+    return BatchedScene(_f32(xyz), _f32(feat), _f32(opa), [cam], [k * n_per_cloud for k in range(n_clouds)],
+                        [n_per_cloud] * n_clouds, name="multisample")
+
+
+def sh_raw(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Raw appearance rows [n, 37] float32 for the appearance step: an opacity
+    logit x ~ N(-0.5, 1.5) (so 1 - exp(-exp(x)) covers (0, 1)), then degree-2
+    SH coefficients (basis-major, 4 channels): band 0 ~ U(0, 2) (a positive
+    base colour after the 0.282 basis value), bands 1 and 2 ~ N(0, 0.3)."""
+    logit = rng.normal(-0.5, 1.5, (n, 1))
+    dc = rng.uniform(0.0, 2.0, (n, 4))
+    hi = rng.normal(0.0, 0.3, (n, 32))
+    return _f32(np.concatenate([logit, dc, hi], axis=1))
 
 
 def make_config(k: int, **kw):
