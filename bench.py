@@ -56,6 +56,19 @@ def stage_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses):
     }
 
 
+def sort_passes(tuning_name: str, which: str, bits: int) -> int:
+    """Radix passes of a sort of ``bits``-bit keys under a tuning entry (the
+    library's rule for "auto" digits: fewest passes of at most 9 bits)."""
+    import re
+    m = re.search(which + r" sort (\d+)-bit", tuning_name)
+    if m:
+        d = int(m.group(1))
+    else:
+        p = (bits + 8) // 9
+        d = max(7, -(-bits // p))
+    return -(-bits // d)
+
+
 def source_digest() -> str:
     """sha256 over the HIP sources, to tell whether stored counters are stale."""
     import glob
@@ -138,13 +151,11 @@ def main():
     tn = pr.tuning_table()
     tid = args.tuning if args.tuning >= 0 else pr.lib().inpc_tuning_for(
         pr.make_views([s.cam], [0], [s.n]), 1, s.n, s.F, 0)
-    import re
-    zdig = int(re.search(r"depth(?: sort)? (\d+)-bit", tn[tid]).group(1))
-    pdig = int(re.search(r"pixel(?: sort)? (\d+)-bit", tn[tid]).group(1))
     zspan = int(np.float32(s.cam.far).view(np.uint32)) - int(np.float32(s.cam.near).view(np.uint32))
-    zpasses = -(-max(1, zspan.bit_length()) // zdig)
+    zbits = max(1, zspan.bit_length())
     pbits = max(1, (P - 1).bit_length())
-    ppasses = -(-pbits // pdig)
+    zpasses = sort_passes(tn[tid], "depth", zbits)
+    ppasses = sort_passes(tn[tid], "pixel", pbits)
     model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses)
     per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in stages.items() if v[1] > 0}
     leaf = {k: v for k, v in per_step.items() if k in model}

@@ -79,8 +79,14 @@ typedef struct {
     float t_threshold; /* early-termination transmittance; 1e-4 in the paper; 0 disables */
     int32_t mode;      /* inpc_bwd_mode_t */
     int32_t tuning_id; /* -1: the autotuner's cached choice (else the default); >= 0: entry of the tuning table */
-    int32_t reserved;  /* must be 0 */
+    int32_t flags;     /* 0 or INPC_ATTR_PER_VIEW_POINT */
 } inpc_settings_t;
+
+/* settings.flags: features and opacities are indexed by view point (row
+ * sum_{u<v} point_count_u + i for point point_offset_v + i of view v) instead
+ * of by point, so every view can carry its own view-dependent features (the
+ * output of inpc_appearance_fwd).  Positions stay indexed by point. */
+#define INPC_ATTR_PER_VIEW_POINT 1
 
 /* One view of a batched call.  View v renders points
  * [point_offset, point_offset + point_count) of the point arrays (views may
@@ -112,12 +118,18 @@ int inpc_batched_sizes(const inpc_view_t *views_host, int32_t n_views, int64_t n
 /* Forward rasterization of one view (Algorithm 1).
  * xyz [N,3] f32, feat [N,F] (feat_dtype), opacity [N] f32 in [0,1];
  * image [H,W,F] f32 and t_final [H,W] f32 are written in full.
+ * blend_weight [N] f32 may be NULL (not computed).  Otherwise it is written
+ * in full: per point, the blend weights T_k alpha_k (Eq. 1) of its blended
+ * splats summed with the splats' bilinear weights as factors (the
+ * bilinear combination of Appendix A.6), the per-point quantity that the
+ * probability-field updates of Section 3.1 (Eq. 2, Eq. 3) consume; exact 0
+ * for points without a blended splat.
  * saved (saved_bytes) receives the state the backward needs; ws is scratch. */
 int inpc_rasterize_fwd(const float *xyz, const void *feat, int32_t feat_dtype,
                        const float *opacity, int64_t n_points, int32_t F,
                        const inpc_camera_t *cam_host, const inpc_settings_t *settings_host,
-                       float *image, float *t_final, void *saved, size_t saved_bytes, void *ws,
-                       size_t ws_bytes, void *stream);
+                       float *image, float *t_final, float *blend_weight, void *saved,
+                       size_t saved_bytes, void *ws, size_t ws_bytes, void *stream);
 
 /* Backward of inpc_rasterize_fwd for L with dL/dimage = grad_image [H,W,F]
  * and dL/dt_final = grad_t_final [H,W] (may be NULL = zero).  The inputs and
@@ -137,15 +149,16 @@ int inpc_rasterize_bwd(const float *xyz, const void *feat, int32_t feat_dtype,
 /* Forward over several views of uneven size and point count in one launch
  * sequence: one projection, one global depth sort, one fragment emission,
  * one global pixel sort and one blend for all views.  Packed outputs:
- * image [sum P_v, F], t_final [sum P_v].  n_points is the length of the
+ * image [sum P_v, F], t_final [sum P_v], blend_weight (NULL or one entry per
+ * view point, in view order) [sum point_count_v].  n_points is the length of the
  * point arrays.  The view table is read on the host and passed to the
  * kernels by value, so the call can be graph-captured. */
 int inpc_rasterize_fwd_batched(const float *xyz, const void *feat, int32_t feat_dtype,
                                const float *opacity, int64_t n_points, int32_t F,
                                const inpc_view_t *views_host, int32_t n_views,
                                const inpc_settings_t *settings_host, float *image,
-                               float *t_final, void *saved, size_t saved_bytes, void *ws,
-                               size_t ws_bytes, void *stream);
+                               float *t_final, float *blend_weight, void *saved,
+                               size_t saved_bytes, void *ws, size_t ws_bytes, void *stream);
 
 /* Backward of the batched forward.  Gradients are per *view point*: row
  * (sum_{u<v} point_count_u) + i belongs to point point_offset_v + i of view
@@ -158,6 +171,54 @@ int inpc_rasterize_bwd_batched(const float *xyz, const void *feat, int32_t feat_
                                size_t saved_bytes, const float *grad_image,
                                const float *grad_t_final, float *grad_feat,
                                float *grad_opacity, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ appearance */
+
+/* Per-point appearance step (Section 3.3).  raw [N,37] f32 per point: the
+ * opacity logit x, then 36 coefficients of real spherical harmonics of
+ * degree 2 for 4 output channels, coefficient (basis j, channel c) at
+ * 1 + 4j + c; basis order (l,m) = (0,0),(1,-1),(1,0),(1,1),(2,-2),(2,-1),
+ * (2,0),(2,1),(2,2), the real harmonics being sqrt(2) Re / Im of the
+ * complex ones with the Condon-Shortley phase.
+ * Forward, per view point (views as in the batched calls; pixel offsets must
+ * be packed): opacity [sum point_count] f32 = 1 - exp(-exp(x)), and the
+ * 4-D feature [sum point_count, 4] (feat_dtype; bfloat16 rounded to nearest
+ * even) = sum_j Y_j(d) coef[j][c], d the unit vector from the view's camera
+ * centre -R^T t to the point (zero for a point at the centre).  These rows
+ * feed the rasterizer with INPC_ATTR_PER_VIEW_POINT.
+ * Backward: grad_raw [N,37] f32, written in full, = the sum over the views
+ * containing each point (in view order) of the chain rule through both
+ * parts; points in no view get zeros.  Positions get no gradient.
+ * ws: at least 256 * n_views bytes of device scratch (the view table). */
+int inpc_appearance_fwd(const float *xyz, const float *raw, int64_t n_points,
+                        const inpc_view_t *views_host, int32_t n_views, float *opacity,
+                        void *feat, int32_t feat_dtype, void *ws, size_t ws_bytes, void *stream);
+int inpc_appearance_bwd(const float *xyz, const float *raw, int64_t n_points,
+                        const inpc_view_t *views_host, int32_t n_views,
+                        const float *grad_opacity, const float *grad_feat, float *grad_raw,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* --------------------------------------------------------- multisampling */
+
+/* Multisampled inference (Section 3.2: for one viewpoint, several point
+ * clouds are sampled and rasterized, and each pixel's features are
+ * averaged).  Cloud k is the range [cloud_offset[k], +cloud_count[k]) of the
+ * point arrays (host arrays; 1 <= n_clouds <= 4096; clouds may overlap).
+ * image [H,W,F] f32 receives the per-pixel mean of the K feature images and
+ * t_final [H,W] f32 the mean of the K final transmittances (compositing over
+ * a background is linear, so the mean of composited images equals the mean
+ * image composited with the mean transmittance).  Means are summed in f64
+ * in cloud order.  Forward only; settings->mode is validated but no backward
+ * state is kept.  ws: inpc_multisample_sizes() bytes, 256-byte aligned. */
+int inpc_multisample_sizes(int64_t n_points, const inpc_camera_t *cam_host,
+                           const int64_t *cloud_offset_host, const int64_t *cloud_count_host,
+                           int32_t n_clouds, int32_t F, int32_t feat_dtype, size_t *ws_bytes);
+int inpc_multisample_fwd(const float *xyz, const void *feat, int32_t feat_dtype,
+                         const float *opacity, int64_t n_points, int32_t F,
+                         const inpc_camera_t *cam_host, const int64_t *cloud_offset_host,
+                         const int64_t *cloud_count_host, int32_t n_clouds,
+                         const inpc_settings_t *settings_host, float *image, float *t_final,
+                         void *ws, size_t ws_bytes, void *stream);
 
 /* grad_feat[p] = sum over views v containing p, in view order, of the view
  * point rows of p (and likewise grad_opacity).  Points no view contains get

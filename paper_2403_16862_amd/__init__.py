@@ -51,7 +51,7 @@ class CCamera(ctypes.Structure):
 
 class CSettings(ctypes.Structure):
     _fields_ = [("t_threshold", ctypes.c_float), ("mode", ctypes.c_int32),
-                ("tuning_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tuning_id", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class CView(ctypes.Structure):
@@ -77,12 +77,17 @@ def lib():
     sig = {
         "inpc_plain_sizes": [i64, cam_p, i32, i32, i32, szp, szp, szp],
         "inpc_batched_sizes": [view_p, i32, i64, i32, i32, i32, szp, szp, szp],
-        "inpc_rasterize_fwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, sz, P, sz, P],
+        "inpc_rasterize_fwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, P, sz, P, sz, P],
         "inpc_rasterize_bwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, sz, P, P, P, P, P, sz, P],
-        "inpc_rasterize_fwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, P, P, sz, P, sz, P],
+        "inpc_rasterize_fwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, P, P, P, sz, P, sz,
+                                       P],
         "inpc_rasterize_bwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, sz, P, P, P, P, P,
                                        sz, P],
         "inpc_sum_view_grads": [view_p, i32, i64, i32, P, P, P, P, P, sz, P],
+        "inpc_multisample_sizes": [i64, cam_p, P, P, i32, i32, i32, szp],
+        "inpc_appearance_fwd": [P, P, i64, view_p, i32, P, P, i32, P, sz, P],
+        "inpc_appearance_bwd": [P, P, i64, view_p, i32, P, P, P, P, sz, P],
+        "inpc_multisample_fwd": [P, P, i32, P, i64, i32, cam_p, P, P, i32, set_p, P, P, P, sz, P],
         "inpc_tuning_count": [],
         "inpc_tuning_name": [i32],
         "inpc_autotune": [P, P, i32, P, i64, i32, view_p, i32, ctypes.c_float, P, P, P, sz, P, P, P, P, sz,
@@ -148,12 +153,15 @@ def c_views(cams: Sequence, point_offsets: Sequence[int], point_counts: Sequence
     return arr, pix
 
 
-def c_settings(t_threshold: float, mode: int, tuning_id: int) -> CSettings:
+ATTR_PER_VIEW_POINT = 1   # settings flag: features / opacities indexed by view point
+
+
+def c_settings(t_threshold: float, mode: int, tuning_id: int, flags: int = 0) -> CSettings:
     s = CSettings()
     s.t_threshold = float(t_threshold)
     s.mode = int(mode)
     s.tuning_id = int(tuning_id)
-    s.reserved = 0
+    s.flags = int(flags)
     return s
 
 
@@ -186,15 +194,18 @@ def _buffer(nbytes: int, device) -> torch.Tensor:
     return t[off:off + max(int(nbytes), 1)]
 
 
-def _check_points(xyz: torch.Tensor, feat: torch.Tensor, opa: torch.Tensor):
+def _check_points(xyz: torch.Tensor, feat: torch.Tensor, opa: torch.Tensor, n_attr=None):
+    """n_attr: rows of feat / opa when they are indexed by view point (else N)."""
     if not (xyz.is_cuda and feat.is_cuda and opa.is_cuda):
         raise ValueError("xyz, feat and opa must be device tensors")
     if xyz.dtype != torch.float32 or opa.dtype != torch.float32:
         raise TypeError("xyz and opacity must be float32")
     if xyz.dim() != 2 or xyz.shape[1] != 3 or feat.dim() != 2 or opa.dim() != 1:
         raise ValueError("expected xyz [N,3], feat [N,F], opa [N]")
-    if not (xyz.shape[0] == feat.shape[0] == opa.shape[0]):
-        raise ValueError("xyz, feat and opa disagree on N")
+    rows = xyz.shape[0] if n_attr is None else n_attr
+    if not (rows == feat.shape[0] == opa.shape[0]):
+        raise ValueError("feat and opa must have one row per point (per view point with "
+                         "attr_per_view_point)")
 
 
 # ------------------------------------------------------------------ plain calls
@@ -229,17 +240,44 @@ class ForwardState:
 
 
 def rasterize_forward(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save",
-                      tuning_id: int = -1, keep_workspace: bool = False):
-    """Forward only; returns (image [H,W,F], t_final [H,W], ForwardState)."""
+                      tuning_id: int = -1, keep_workspace: bool = False, blend_weight=None):
+    """Forward only; returns (image [H,W,F], t_final [H,W], ForwardState).
+
+    ``blend_weight``: optional float32 [N] device tensor that receives each
+    point's blend weight (its splats' T*alpha summed with the bilinear
+    weights as factors)."""
     _check_points(xyz, feat, opa)
     xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
     cams = [cam]
     views, P = c_views(cams, [0], [xyz.shape[0]])
     return _forward(xyz, feat, opa, views, 1, t_threshold, mode, tuning_id, keep_workspace,
-                    (views[0].cam.height, views[0].cam.width))
+                    (views[0].cam.height, views[0].cam.width), blend_weight)
 
 
-def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_workspace, img_hw):
+def rasterize_forward_batched(xyz, feat, opa, views, t_threshold: float = 1e-4, mode="save",
+                              tuning_id: int = -1, keep_workspace: bool = False, blend_weight=None,
+                              attr_per_view_point: bool = False):
+    """Forward of a packed view table (``make_views``); returns packed
+    (image [sum P, F], t_final [sum P], ForwardState).  ``blend_weight``:
+    optional float32 tensor with one entry per view point."""
+    _check_points(xyz, feat, opa, _n_vp(views) if attr_per_view_point else None)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    return _forward(xyz, feat, opa, views, len(views), t_threshold, mode, tuning_id, keep_workspace, None,
+                    blend_weight, ATTR_PER_VIEW_POINT if attr_per_view_point else 0)
+
+
+def _check_blend_weight(bw, views, n_views, dev):
+    if bw is None:
+        return
+    nvp = sum(int(views[i].point_count) for i in range(n_views))
+    if (bw.dtype != torch.float32 or bw.numel() != nvp or not bw.is_contiguous()
+            or bw.device != dev):
+        raise ValueError("blend_weight must be a contiguous float32 tensor with one entry per "
+                         "view point, on the points' device")
+
+
+def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_workspace, img_hw,
+             blend_weight=None, flags: int = 0):
     m = _mode(mode)
     fdt = _fdt(feat)
     F = int(feat.shape[1])
@@ -255,10 +293,12 @@ def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_
     else:
         image = torch.empty((P, F), dtype=torch.float32, device=dev)
         t_final = torch.empty((P,), dtype=torch.float32, device=dev)
-    st = c_settings(t_threshold, m, tuning_id)
+    st = c_settings(t_threshold, m, tuning_id, flags)
+    _check_blend_weight(blend_weight, views, n_views, dev)
     _check(lib().inpc_rasterize_fwd_batched(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, views, n_views,
-                                            ctypes.byref(st), _ptr(image), _ptr(t_final), _ptr(saved),
-                                            saved.numel(), _ptr(ws), ws.numel(), _stream()),
+                                            ctypes.byref(st), _ptr(image), _ptr(t_final),
+                                            _ptr(blend_weight), _ptr(saved), saved.numel(), _ptr(ws),
+                                            ws.numel(), _stream()),
            "inpc_rasterize_fwd")
     state = ForwardState(saved, ws if keep_workspace else None, st, views, n_views, N, F, fdt)
     return image, t_final, state
@@ -286,9 +326,9 @@ def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None):
 
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xyz, feat, opa, views, n_views, img_hw, t_threshold, mode, tuning_id, fold):
+    def forward(ctx, xyz, feat, opa, views, n_views, img_hw, t_threshold, mode, tuning_id, fold, flags):
         image, t_final, state = _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id,
-                                         False, img_hw)
+                                         False, img_hw, None, flags)
         ctx.state = state
         ctx.fold = fold
         ctx.set_materialize_grads(False)
@@ -300,14 +340,14 @@ class _Rasterize(torch.autograd.Function):
         xyz, feat, opa = ctx.saved_tensors
         st = ctx.state
         if g_img is None and g_t is None:
-            return (None,) * 10
+            return (None,) * 11
         if g_img is None:
             P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
             g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
         gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
         if ctx.fold:
             gf, go = sum_view_grads(st.views, st.n_views, st.n_points, gf, go)
-        return None, gf, go, None, None, None, None, None, None, None
+        return None, gf, go, None, None, None, None, None, None, None, None
 
 
 def rasterize(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1):
@@ -316,7 +356,7 @@ def rasterize(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save", tunin
     xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
     views, _ = c_views([cam], [0], [xyz.shape[0]])
     hw = (views[0].cam.height, views[0].cam.width)
-    return _Rasterize.apply(xyz, feat, opa, views, 1, hw, t_threshold, mode, tuning_id, False)
+    return _Rasterize.apply(xyz, feat, opa, views, 1, hw, t_threshold, mode, tuning_id, False, 0)
 
 
 def make_views(cams: Sequence, point_offsets: Sequence[int], point_counts: Sequence[int]):
@@ -335,16 +375,19 @@ def _is_identity_layout(views, n_views, n_points) -> bool:
 
 
 def rasterize_batched(xyz, feat, opa, views, t_threshold: float = 1e-4, mode="save",
-                      tuning_id: int = -1):
+                      tuning_id: int = -1, attr_per_view_point: bool = False):
     """Differentiable batched rasterization -> packed (image [sum P,F], t_final [sum P]).
 
     ``views`` comes from ``make_views``.  Gradients w.r.t. feat/opa are folded
-    onto the points (views sharing points are summed in view order)."""
-    _check_points(xyz, feat, opa)
+    onto the points (views sharing points are summed in view order).  With
+    ``attr_per_view_point`` feat and opa hold one row per view point (views
+    in order) and their gradients keep that layout."""
+    _check_points(xyz, feat, opa, _n_vp(views) if attr_per_view_point else None)
     xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
     n_views = len(views)
-    fold = not _is_identity_layout(views, n_views, xyz.shape[0])
-    return _Rasterize.apply(xyz, feat, opa, views, n_views, None, t_threshold, mode, tuning_id, fold)
+    flags = ATTR_PER_VIEW_POINT if attr_per_view_point else 0
+    fold = not attr_per_view_point and not _is_identity_layout(views, n_views, xyz.shape[0])
+    return _Rasterize.apply(xyz, feat, opa, views, n_views, None, t_threshold, mode, tuning_id, fold, flags)
 
 
 def sum_view_grads(views, n_views: int, n_points: int, vg_feat, vg_opa):
@@ -357,6 +400,139 @@ def sum_view_grads(views, n_views: int, n_points: int, vg_feat, vg_opa):
                                      _ptr(vg_opa.contiguous()), _ptr(gf), _ptr(go), _ptr(ws), ws.numel(),
                                      _stream()), "inpc_sum_view_grads")
     return gf, go
+
+
+# ---------------------------------------------------------------- appearance
+N_RAW = 37   # opacity logit + 9 SH basis functions x 4 channels
+
+
+def _n_vp(views) -> int:
+    return sum(int(views[i].point_count) for i in range(len(views)))
+
+
+def appearance_forward(xyz, raw, views, feat_dtype=torch.float32):
+    """Opacity activation and degree-2 SH features per view point:
+    returns (opacity [n_vp] f32, feat [n_vp, 4] in ``feat_dtype``)."""
+    if raw.dtype != torch.float32 or raw.dim() != 2 or raw.shape[1] != N_RAW:
+        raise TypeError("raw must be float32 [N, 37]")
+    if xyz.dtype != torch.float32 or not (xyz.is_cuda and raw.is_cuda):
+        raise TypeError("xyz and raw must be float32 device tensors")
+    xyz, raw = xyz.contiguous(), raw.contiguous()
+    n = _n_vp(views)
+    dev = xyz.device
+    opa = torch.empty((n,), dtype=torch.float32, device=dev)
+    feat = torch.empty((n, 4), dtype=feat_dtype, device=dev)
+    ws = _buffer(256 * len(views), dev)
+    _check(lib().inpc_appearance_fwd(_ptr(xyz), _ptr(raw), int(xyz.shape[0]), views, len(views), _ptr(opa),
+                                     _ptr(feat), _fdt(feat), _ptr(ws), ws.numel(), _stream()),
+           "inpc_appearance_fwd")
+    return opa, feat
+
+
+def appearance_backward(xyz, raw, views, g_opa, g_feat):
+    """Gradient of the raw rows [N, 37] (view points of a point summed in view order)."""
+    xyz, raw = xyz.contiguous(), raw.contiguous()
+    dev = xyz.device
+    n = _n_vp(views)
+    g_opa = (torch.zeros((n,), dtype=torch.float32, device=dev) if g_opa is None
+             else g_opa.contiguous().float())
+    g_feat = (torch.zeros((n, 4), dtype=torch.float32, device=dev) if g_feat is None
+              else g_feat.contiguous().float())
+    grad = torch.empty((xyz.shape[0], N_RAW), dtype=torch.float32, device=dev)
+    ws = _buffer(256 * len(views), dev)
+    _check(lib().inpc_appearance_bwd(_ptr(xyz), _ptr(raw), int(xyz.shape[0]), views, len(views),
+                                     _ptr(g_opa), _ptr(g_feat), _ptr(grad), _ptr(ws), ws.numel(), _stream()),
+           "inpc_appearance_bwd")
+    return grad
+
+
+class _Appearance(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xyz, raw, views):
+        opa, feat = appearance_forward(xyz, raw, views)
+        ctx.views = views
+        ctx.save_for_backward(xyz, raw)
+        ctx.set_materialize_grads(False)
+        return opa, feat
+
+    @staticmethod
+    def backward(ctx, g_opa, g_feat):
+        xyz, raw = ctx.saved_tensors
+        if g_opa is None and g_feat is None:
+            return None, None, None
+        return None, appearance_backward(xyz, raw, ctx.views, g_opa, g_feat), None
+
+
+def appearance(xyz, raw, views):
+    """Differentiable appearance step -> (opacity [n_vp], feat [n_vp, 4]) in float32."""
+    return _Appearance.apply(xyz, raw, views)
+
+
+class _ShRaster(torch.autograd.Function):
+    """Appearance step fused with the batched rasterizer: gradients flow from
+    the image to the raw rows in float32 even when the features are stored as
+    bfloat16."""
+
+    @staticmethod
+    def forward(ctx, xyz, raw, views, t_threshold, mode, tuning_id, feat_dtype):
+        opa, feat = appearance_forward(xyz, raw, views, feat_dtype)
+        image, t_final, state = _forward(xyz, feat, opa, views, len(views), t_threshold, mode, tuning_id,
+                                         False, None, None, ATTR_PER_VIEW_POINT)
+        ctx.state = state
+        ctx.views = views
+        ctx.save_for_backward(xyz, raw, feat, opa)
+        ctx.set_materialize_grads(False)
+        return image, t_final
+
+    @staticmethod
+    def backward(ctx, g_img, g_t):
+        xyz, raw, feat, opa = ctx.saved_tensors
+        if g_img is None and g_t is None:
+            return (None,) * 7
+        st = ctx.state
+        if g_img is None:
+            P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
+            g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
+        gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
+        return None, appearance_backward(xyz, raw, ctx.views, go, gf), None, None, None, None, None
+
+
+def render_sh(xyz, raw, views, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1,
+              feat_dtype=torch.float32):
+    """Appearance step (opacity activation + degree-2 SH, per view point) then
+    batched rasterization -> packed (image [sum P, 4], t_final [sum P]);
+    differentiable with respect to ``raw`` [N, 37]."""
+    if xyz.dtype != torch.float32 or not xyz.is_cuda:
+        raise TypeError("xyz must be a float32 device tensor")
+    return _ShRaster.apply(xyz.contiguous(), raw.contiguous(), views, t_threshold, mode, tuning_id, feat_dtype)
+
+
+# ---------------------------------------------------------------- multisampling
+def multisample(xyz, feat, opa, cam, cloud_offsets: Sequence[int], cloud_counts: Sequence[int],
+                t_threshold: float = 1e-4, tuning_id: int = -1):
+    """Renders K point clouds (ranges of the point arrays) for one camera and
+    returns the per-pixel means (image [H,W,F], t_final [H,W])."""
+    _check_points(xyz, feat, opa)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    K = len(cloud_offsets)
+    if K != len(cloud_counts) or K < 1:
+        raise ValueError("need one offset and one count per cloud")
+    off = (ctypes.c_int64 * K)(*[int(o) for o in cloud_offsets])
+    cnt = (ctypes.c_int64 * K)(*[int(c) for c in cloud_counts])
+    c = c_camera(cam)
+    F, fdt, N = int(feat.shape[1]), _fdt(feat), int(xyz.shape[0])
+    need = ctypes.c_size_t(0)
+    _check(lib().inpc_multisample_sizes(N, ctypes.byref(c), off, cnt, K, F, fdt, ctypes.byref(need)),
+           "inpc_multisample_sizes")
+    dev = xyz.device
+    ws = _buffer(need.value, dev)
+    image = torch.empty((c.height, c.width, F), dtype=torch.float32, device=dev)
+    t_final = torch.empty((c.height, c.width), dtype=torch.float32, device=dev)
+    st = c_settings(t_threshold, 1, tuning_id)
+    _check(lib().inpc_multisample_fwd(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, ctypes.byref(c), off, cnt,
+                                      K, ctypes.byref(st), _ptr(image), _ptr(t_final), _ptr(ws), ws.numel(),
+                                      _stream()), "inpc_multisample_fwd")
+    return image, t_final
 
 
 # ---------------------------------------------------------------- tuning, debug
@@ -457,13 +633,15 @@ class BatchedStep:
     """
 
     def __init__(self, xyz, feat, opa, views, g_img, t_threshold: float = 1e-4, mode="save",
-                 tuning_id: int = -1, g_t=None):
+                 tuning_id: int = -1, g_t=None, want_blend_weight: bool = False,
+                 attr_per_view_point: bool = False):
         self.xyz, self.feat, self.opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
         self.views = views
         self.n_views = len(views)
         self.N, self.F, self.fdt = int(xyz.shape[0]), int(feat.shape[1]), _fdt(feat)
         m = _mode(mode)
-        self.settings = c_settings(t_threshold, m, tuning_id)
+        self.settings = c_settings(t_threshold, m, tuning_id,
+                                   ATTR_PER_VIEW_POINT if attr_per_view_point else 0)
         fws, sv, bws = batched_sizes(views, self.n_views, self.N, self.F, self.fdt, m)
         dev = xyz.device
         self.saved = _buffer(sv, dev)
@@ -477,13 +655,16 @@ class BatchedStep:
         self.g_t = None if g_t is None else g_t.contiguous().float()
         self.grad_feat = torch.empty((self.nvp, self.F), dtype=torch.float32, device=dev)
         self.grad_opa = torch.empty((self.nvp,), dtype=torch.float32, device=dev)
+        self.blend_weight = (torch.empty((self.nvp,), dtype=torch.float32, device=dev)
+                             if want_blend_weight else None)
         self.graph = None
 
     def forward(self):
         _check(lib().inpc_rasterize_fwd_batched(
             _ptr(self.xyz), _ptr(self.feat), self.fdt, _ptr(self.opa), self.N, self.F, self.views,
             self.n_views, ctypes.byref(self.settings), _ptr(self.image), _ptr(self.t_final),
-            _ptr(self.saved), self.saved.numel(), _ptr(self.fwd_ws), self.fwd_ws.numel(), _stream()),
+            _ptr(self.blend_weight), _ptr(self.saved), self.saved.numel(), _ptr(self.fwd_ws),
+            self.fwd_ws.numel(), _stream()),
             "inpc_rasterize_fwd_batched")
 
     def backward(self):

@@ -18,18 +18,28 @@
 namespace inpc {
 
 // ------------------------------------------------------------ tuning table
+// zdigit / pdigit = 0: choose the digit width from the key width (fewest
+// passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
-    {9, 7, 16, 3, "depth sort 9-bit digits, pixel sort 7-bit digits, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {8, 8, 16, 4, "depth 8-bit, pixel 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
-    {9, 8, 16, 4, "depth 9-bit, pixel 8-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
-    {9, 7, 32, 3, "depth 9-bit, pixel 7-bit, 8192-key tiles, blend 8 lanes/pixel 4x2"},
-    {9, 7, 16, 4, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 16 lanes/pixel 2x2"},
-    {9, 11, 16, 3, "depth 9-bit, pixel 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {9, 7, 16, 2, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {9, 7, 16, 1, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 2 lanes/pixel 8x4"},
-    {9, 7, 16, 0, "depth 9-bit, pixel 7-bit, 4096-key tiles, blend 1 lane/pixel 8x8"},
-    {10, 11, 16, 3, "depth 10-bit, pixel 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {0, 0, 16, 3, "depth and pixel sort auto digits, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {0, 0, 16, 4, "depth and pixel sort auto digits, 4096-key tiles, blend 16 lanes/pixel 2x2"},
+    {0, 0, 32, 3, "depth and pixel sort auto digits, 8192-key tiles, blend 8 lanes/pixel 4x2"},
+    {8, 8, 16, 3, "depth sort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {9, 11, 16, 3, "depth sort 9-bit, pixel sort 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
+    {0, 0, 16, 2, "depth and pixel sort auto digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {0, 0, 16, 1, "depth and pixel sort auto digits, 4096-key tiles, blend 2 lanes/pixel 8x4"},
+    {0, 0, 16, 0, "depth and pixel sort auto digits, 4096-key tiles, blend 1 lane/pixel 8x8"},
 };
+
+int auto_digit(int bits) {
+    if (bits <= 0) return 8;
+    const int passes = (bits + 8) / 9;
+    const int d = (bits + passes - 1) / passes;
+    return d < 7 ? 7 : d;
+}
+
+static int zdigit_of(const Tuning& t, int bits) { return t.zdigit ? t.zdigit : auto_digit(bits); }
+static int pdigit_of(const Tuning& t, int bits) { return t.pdigit ? t.pdigit : auto_digit(bits); }
 constexpr int kNumTunings = (int)(sizeof(kTunings) / sizeof(kTunings[0]));
 constexpr int kDefaultTuning = 0;
 
@@ -80,7 +90,7 @@ static int check_camera(const inpc_camera_t& c) {
 // Builds the problem description from a host view table; the blend shape
 // decides the tile grid, so it is part of the problem.
 static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points, int F, int fdt,
-                        int mode, int shape, Problem& pb) {
+                        int mode, int shape, Problem& pb, bool attr_per_vp = false) {
     if (!views || n_views < 1 || n_points < 0) return INPC_EINVAL;
     if (n_views > 65536) return INPC_EUNSUPPORTED;
     if (F < 1 || F > 64) return INPC_EUNSUPPORTED;
@@ -109,6 +119,7 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
         g.W = in.cam.width; g.H = in.cam.height;
         g.point_offset = in.point_offset;
         g.vpoint_offset = vp;
+        g.attr_offset = attr_per_vp ? vp : in.point_offset;
         g.point_count = in.point_count;
         g.pixel_offset = pix;
         g.tile_offset = tiles;
@@ -179,8 +190,8 @@ static size_t max_counts_words(const Problem& pb) {
     size_t w = 0;
     for (int i = 0; i < kNumTunings; ++i) {
         const Tuning& t = kTunings[i];
-        w = std::max(w, sort_counts_words(t.zdigit, t.sort_items, pb.n_vp));
-        w = std::max(w, sort_counts_words(t.pdigit, t.sort_items, 4 * pb.n_vp));
+        w = std::max(w, sort_counts_words(zdigit_of(t, pb.zbits), t.sort_items, pb.n_vp));
+        w = std::max(w, sort_counts_words(pdigit_of(t, pb.pixel_bits), t.sort_items, 4 * pb.n_vp));
     }
     return w;
 }
@@ -237,7 +248,8 @@ static T* at(void* base, size_t off) {
 // ------------------------------------------------------------ profiling
 static const char* kStageNames[kNumStages] = {
     "project", "depth_sort", "emit", "pixel_sort", "ranges", "blend_fwd", "clear_records",
-    "blend_bwd", "point_reduce", "sort_upsweep", "sort_scan", "sort_downsweep", "view_grads"};
+    "blend_bwd", "point_reduce", "sort_upsweep", "sort_scan", "sort_downsweep", "view_grads",
+    "blend_weight", "mean_planes", "appearance_fwd", "appearance_bwd"};
 
 const char* stage_name(int st) { return (st >= 0 && st < kNumStages) ? kStageNames[st] : ""; }
 
@@ -336,15 +348,16 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* counts = at<uint32_t>(build_base, bo.counts);
     {
         ProfScope p(kStDepthSort, s);
-        launch_radix_sort(tn.zdigit, tn.sort_items, pb.zbits, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, nullptr,
-                          pb.n_vp, counts, s);
+        launch_radix_sort(zdigit_of(tn, pb.zbits), tn.sort_items, pb.zbits, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b,
+                          nullptr, pb.n_vp, counts, s);
     }
-    const int zp = radix_passes(tn.zdigit, pb.zbits);
+    const int zp = radix_passes(zdigit_of(tn, pb.zbits), pb.zbits);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
 
     // Pixel sort: emission writes (kb, vb); the sorted ids must end in the
     // fragment-state id buffer.
-    const int pp = radix_passes(tn.pdigit, pb.pixel_bits);
+    const int pdig = pdigit_of(tn, pb.pixel_bits);
+    const int pp = radix_passes(pdig, pb.pixel_bits);
     uint32_t* ids_final = at<uint32_t>(frag_base, fo.ids);
     uint32_t* pv_other = at<uint32_t>(build_base, bo.pv_other);
     uint32_t* pk_a = at<uint32_t>(build_base, bo.pk_a);
@@ -358,7 +371,7 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     }
     {
         ProfScope p(kStPixelSort, s);
-        launch_radix_sort(tn.pdigit, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
+        launch_radix_sort(pdig, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
                           m_dev, 4 * pb.n_vp, counts, s);
     }
     const uint32_t* pk_sorted = (pp & 1) ? pk_a : pk_b;
@@ -370,8 +383,8 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
 
 // ------------------------------------------------------------- forward
 static int forward(const Problem& pb, int tid, const float* xyz, const void* feat,
-                   const float* opacity, float tau, float* image, float* t_final, void* saved,
-                   size_t saved_bytes, void* ws, size_t ws_bytes, hipStream_t s) {
+                   const float* opacity, float tau, float* image, float* t_final, float* blend_weight,
+                   void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, hipStream_t s) {
     const Layout L = make_layout(pb);
     if (saved_bytes < L.saved_bytes || ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
     if (pb.n_pixels > 0 && (!saved || !ws)) return INPC_EINVAL;
@@ -380,12 +393,23 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
     build_fragments(pb, tn, xyz, opacity, frag_base, fo, ws, L.fwd_build, m_dev, s);
-    ProfScope p(kStBlendFwd, s);
-    launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
-                     (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
-                     at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
-                     image, t_final, at<PixelState>(saved, L.s_state),
-                     pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr, s);
+    // Per-splat blend weights (indexed by splat id) reuse the pixel sort's
+    // spare value buffer, which is dead once the sort has finished.
+    float* splat_weight = blend_weight ? at<float>(ws, L.fwd_build.pv_other) : nullptr;
+    if (splat_weight)
+        launch_fill_u32(reinterpret_cast<uint32_t*>(splat_weight), 0u, (size_t)4 * pb.n_vp, s);
+    {
+        ProfScope p(kStBlendFwd, s);
+        launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
+                         (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
+                         at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
+                         image, t_final, at<PixelState>(saved, L.s_state),
+                         pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr, splat_weight, s);
+    }
+    if (blend_weight) {
+        ProfScope p(kStBlendWeight, s);
+        launch_blend_weight(pb.n_vp, at<PointRec>(frag_base, fo.rec), splat_weight, blend_weight, s);
+    }
     return check_launch("inpc forward");
 }
 
@@ -439,9 +463,11 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
 
 static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-static int check_settings(const inpc_settings_t* st, int* tuning_req, float* tau, int* mode) {
+static int check_settings(const inpc_settings_t* st, int* tuning_req, float* tau, int* mode,
+                          bool* attr_vp = nullptr) {
     if (!st) return INPC_EINVAL;
-    if (st->reserved != 0) return INPC_EINVAL;
+    if ((st->flags & ~INPC_ATTR_PER_VIEW_POINT) != 0) return INPC_EINVAL;
+    if (attr_vp) *attr_vp = (st->flags & INPC_ATTR_PER_VIEW_POINT) != 0;
     if (!std::isfinite(st->t_threshold) || st->t_threshold < 0.0f) return INPC_EINVAL;
     if (st->tuning_id < -1 || st->tuning_id >= kNumTunings) return INPC_EINVAL;
     if (st->mode != INPC_SAVE && st->mode != INPC_RECOMPUTE) return INPC_EINVAL;
@@ -484,26 +510,112 @@ static int sizes_impl(const inpc_view_t* views, int n_views, int64_t n_points, i
 
 static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
                     int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
-                    float* image, float* t_final, void* saved, size_t saved_bytes, void* ws,
-                    size_t ws_bytes, void* stream) {
+                    float* image, float* t_final, float* blend_weight, void* saved, size_t saved_bytes,
+                    void* ws, size_t ws_bytes, void* stream) {
     int treq, mode;
     float tau;
-    int rc = check_settings(st, &treq, &tau, &mode);
+    bool avp;
+    int rc = check_settings(st, &treq, &tau, &mode, &avp);
     if (rc) return rc;
     Problem pb;
-    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb);
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb, avp);
     if (rc) return rc;
     const int tid = resolve_tuning(treq, pb);
     if (shape_of(tid) != 0) {
-        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb);
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb, avp);
         if (rc) return rc;
     }
     rc = check_arrays(pb, xyz, feat, opa);
     if (rc) return rc;
     if (!image || !t_final || !aligned(image, 16) || !aligned(t_final, 4)) return INPC_EINVAL;
+    if (blend_weight && !aligned(blend_weight, 4)) return INPC_EINVAL;
     if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
-    return forward(pb, tid, xyz, feat, opa, tau, image, t_final, saved, saved_bytes, ws, ws_bytes,
-                   static_cast<hipStream_t>(stream));
+    return forward(pb, tid, xyz, feat, opa, tau, image, t_final, blend_weight, saved, saved_bytes, ws,
+                   ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------ multisampling
+// K point clouds sampled for one camera are rasterized as K views of that
+// camera in one batched forward (no backward state is kept), then the K
+// feature images and transmittances are averaged per pixel.
+static int ms_views(const inpc_camera_t* cam, const int64_t* off, const int64_t* cnt, int K,
+                    std::vector<inpc_view_t>& v) {
+    if (!cam || !off || !cnt || K < 1) return INPC_EINVAL;
+    if (K > 4096) return INPC_EUNSUPPORTED;
+    const int64_t P = (int64_t)cam->width * cam->height;
+    v.assign(K, inpc_view_t{});
+    for (int k = 0; k < K; ++k) {
+        v[k].cam = *cam;
+        v[k].point_offset = off[k];
+        v[k].point_count = cnt[k];
+        v[k].pixel_offset = (int64_t)k * P;
+    }
+    return INPC_OK;
+}
+
+struct MsLayout {
+    Layout L;
+    size_t saved, fwd, img, tf, total;
+};
+
+static MsLayout ms_layout(const Problem& pb) {
+    MsLayout m;
+    m.L = make_layout(pb);
+    Carver c;
+    m.saved = c.take(m.L.saved_bytes);
+    m.fwd = c.take(m.L.fwd_bytes);
+    m.img = c.take((size_t)pb.n_pixels * pb.F * 4);
+    m.tf = c.take((size_t)pb.n_pixels * 4);
+    m.total = c.off;
+    return m;
+}
+
+static int ms_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points, int F,
+                   const inpc_camera_t* cam, const int64_t* off, const int64_t* cnt, int K,
+                   const inpc_settings_t* st, float* image, float* t_final, void* ws, size_t ws_bytes,
+                   size_t* ws_needed, void* stream) {
+    std::vector<inpc_view_t> views;
+    int rc = ms_views(cam, off, cnt, K, views);
+    if (rc) return rc;
+    int treq = -1, mode = INPC_RECOMPUTE;
+    float tau = 1e-4f;
+    bool avp = false;
+    if (!ws_needed) {
+        rc = check_settings(st, &treq, &tau, &mode, &avp);
+        if (rc) return rc;
+    }
+    Problem pb;
+    rc = make_problem(views.data(), K, n_points, F, fdt, INPC_RECOMPUTE, 0, pb, avp);
+    if (rc) return rc;
+    if (ws_needed) {
+        *ws_needed = ms_layout(pb).total;
+        return INPC_OK;
+    }
+    const int tid = resolve_tuning(treq, pb);
+    if (shape_of(tid) != 0) {
+        rc = make_problem(views.data(), K, n_points, F, fdt, INPC_RECOMPUTE, shape_of(tid), pb, avp);
+        if (rc) return rc;
+    }
+    rc = check_arrays(pb, xyz, feat, opa);
+    if (rc) return rc;
+    if (!image || !t_final || !aligned(image, 16) || !aligned(t_final, 4)) return INPC_EINVAL;
+    if (ws && !aligned(ws, 256)) return INPC_EINVAL;
+    const MsLayout m = ms_layout(pb);
+    if (ws_bytes < m.total) return INPC_EWORKSPACE;
+    if (!ws) return INPC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* img_k = at<float>(ws, m.img);
+    float* tf_k = at<float>(ws, m.tf);
+    rc = forward(pb, tid, xyz, feat, opa, tau, img_k, tf_k, nullptr, at<void>(ws, m.saved), m.L.saved_bytes,
+                 at<void>(ws, m.fwd), m.L.fwd_bytes, s);
+    if (rc) return rc;
+    const int64_t P = (int64_t)cam->width * cam->height;
+    {
+        ProfScope p(kStMeanPlanes, s);
+        launch_mean_planes(img_k, K, P * F, image, s);
+        launch_mean_planes(tf_k, K, P, t_final, s);
+    }
+    return check_launch("inpc multisample");
 }
 
 static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
@@ -512,14 +624,15 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
                     float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes, void* stream) {
     int treq, mode;
     float tau;
-    int rc = check_settings(st, &treq, &tau, &mode);
+    bool avp;
+    int rc = check_settings(st, &treq, &tau, &mode, &avp);
     if (rc) return rc;
     Problem pb;
-    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb);
+    rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb, avp);
     if (rc) return rc;
     const int tid = resolve_tuning(treq, pb);
     if (shape_of(tid) != 0) {
-        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb);
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb, avp);
         if (rc) return rc;
     }
     rc = check_arrays(pb, xyz, feat, opa);
@@ -568,12 +681,12 @@ int inpc_batched_sizes(const inpc_view_t* views, int32_t n_views, int64_t n_poin
 
 int inpc_rasterize_fwd(const float* xyz, const void* feat, int32_t fdt, const float* opa,
                        int64_t n_points, int32_t F, const inpc_camera_t* cam,
-                       const inpc_settings_t* st, float* image, float* t_final, void* saved,
-                       size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
+                       const inpc_settings_t* st, float* image, float* t_final, float* blend_weight,
+                       void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
     if (!cam) return INPC_EINVAL;
     const inpc_view_t v = single_view(cam, n_points);
-    return fwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, image, t_final, saved, saved_bytes,
-                    ws, ws_bytes, stream);
+    return fwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, image, t_final, blend_weight, saved,
+                    saved_bytes, ws, ws_bytes, stream);
 }
 
 int inpc_rasterize_bwd(const float* xyz, const void* feat, int32_t fdt, const float* opa,
@@ -590,10 +703,10 @@ int inpc_rasterize_bwd(const float* xyz, const void* feat, int32_t fdt, const fl
 int inpc_rasterize_fwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,
                                int64_t n_points, int32_t F, const inpc_view_t* views,
                                int32_t n_views, const inpc_settings_t* st, float* image,
-                               float* t_final, void* saved, size_t saved_bytes, void* ws,
-                               size_t ws_bytes, void* stream) {
-    return fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, st, image, t_final, saved,
-                    saved_bytes, ws, ws_bytes, stream);
+                               float* t_final, float* blend_weight, void* saved, size_t saved_bytes,
+                               void* ws, size_t ws_bytes, void* stream) {
+    return fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, st, image, t_final, blend_weight,
+                    saved, saved_bytes, ws, ws_bytes, stream);
 }
 
 int inpc_rasterize_bwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,
@@ -623,6 +736,73 @@ int inpc_sum_view_grads(const inpc_view_t* views, int32_t n_views, int64_t n_poi
     launch_upload_views(pb.views.data(), (int)pb.views.size(), dv, s);
     launch_sum_view_grads(dv, (int)pb.views.size(), n_points, F, vg_feat, vg_opa, g_feat, g_opa, s);
     return check_launch("inpc_sum_view_grads");
+}
+
+static int appearance_views(const inpc_view_t* views, int n_views, int64_t n_points, void* ws,
+                            size_t ws_bytes, Problem& pb) {
+    const int rc = make_problem(views, n_views, n_points, 4, INPC_F32, INPC_SAVE, 0, pb);
+    if (rc) return rc;
+    if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
+    if (ws_bytes < pb.views.size() * 256) return INPC_EWORKSPACE;
+    return INPC_OK;
+}
+
+int inpc_appearance_fwd(const float* xyz, const float* raw, int64_t n_points, const inpc_view_t* views,
+                        int32_t n_views, float* opacity, void* feat, int32_t feat_dtype, void* ws,
+                        size_t ws_bytes, void* stream) {
+    Problem pb;
+    int rc = appearance_views(views, n_views, n_points, ws, ws_bytes, pb);
+    if (rc) return rc;
+    if (feat_dtype != INPC_F32 && feat_dtype != INPC_BF16) return INPC_EINVAL;
+    if (n_points > 0 && (!xyz || !raw || !aligned(xyz, 4) || !aligned(raw, 4))) return INPC_EINVAL;
+    if (pb.n_vp > 0 && (!opacity || !feat || !aligned(opacity, 4) || !aligned(feat, 16))) return INPC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GpuView* dv = static_cast<GpuView*>(ws);
+    launch_upload_views(pb.views.data(), (int)pb.views.size(), dv, s);
+    {
+        ProfScope p(kStAppearanceFwd, s);
+        launch_appearance_fwd(xyz, raw, dv, (int)pb.views.size(), pb.n_vp, opacity, feat,
+                              feat_dtype == INPC_BF16, s);
+    }
+    return check_launch("inpc_appearance_fwd");
+}
+
+int inpc_appearance_bwd(const float* xyz, const float* raw, int64_t n_points, const inpc_view_t* views,
+                        int32_t n_views, const float* grad_opacity, const float* grad_feat, float* grad_raw,
+                        void* ws, size_t ws_bytes, void* stream) {
+    Problem pb;
+    int rc = appearance_views(views, n_views, n_points, ws, ws_bytes, pb);
+    if (rc) return rc;
+    if (n_points > 0 && (!xyz || !raw || !grad_raw || !aligned(xyz, 4) || !aligned(raw, 4) ||
+                         !aligned(grad_raw, 4)))
+        return INPC_EINVAL;
+    if (pb.n_vp > 0 && (!grad_opacity || !grad_feat || !aligned(grad_opacity, 4) || !aligned(grad_feat, 16)))
+        return INPC_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GpuView* dv = static_cast<GpuView*>(ws);
+    launch_upload_views(pb.views.data(), (int)pb.views.size(), dv, s);
+    {
+        ProfScope p(kStAppearanceBwd, s);
+        launch_appearance_bwd(xyz, raw, dv, (int)pb.views.size(), n_points, grad_opacity, grad_feat, grad_raw,
+                              s);
+    }
+    return check_launch("inpc_appearance_bwd");
+}
+
+int inpc_multisample_sizes(int64_t n_points, const inpc_camera_t* cam, const int64_t* cloud_offset,
+                           const int64_t* cloud_count, int32_t n_clouds, int32_t F, int32_t fdt,
+                           size_t* ws_bytes) {
+    if (!ws_bytes) return INPC_EINVAL;
+    return ms_impl(nullptr, nullptr, fdt, nullptr, n_points, F, cam, cloud_offset, cloud_count, n_clouds,
+                   nullptr, nullptr, nullptr, nullptr, 0, ws_bytes, nullptr);
+}
+
+int inpc_multisample_fwd(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                         int64_t n_points, int32_t F, const inpc_camera_t* cam, const int64_t* cloud_offset,
+                         const int64_t* cloud_count, int32_t n_clouds, const inpc_settings_t* st,
+                         float* image, float* t_final, void* ws, size_t ws_bytes, void* stream) {
+    return ms_impl(xyz, feat, fdt, opa, n_points, F, cam, cloud_offset, cloud_count, n_clouds, st, image,
+                   t_final, ws, ws_bytes, nullptr, stream);
 }
 
 int inpc_tuning_count(void) { return kNumTunings; }
@@ -760,8 +940,8 @@ int inpc_autotune(const float* xyz, const void* feat, int32_t fdt, const float* 
     for (int tid = 0; tid < kNumTunings; ++tid) {
         inpc_settings_t st{tau, INPC_SAVE, tid, 0};
         auto step = [&]() -> int {
-            int r = fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, image, t_final, saved,
-                             saved_bytes, ws, ws_bytes, stream);
+            int r = fwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, image, t_final, nullptr,
+                             saved, saved_bytes, ws, ws_bytes, stream);
             if (r || !g_img) return r;
             return bwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, saved, saved_bytes,
                             g_img, nullptr, grad_feat, grad_opa, ws, ws_bytes, stream);

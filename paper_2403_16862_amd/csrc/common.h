@@ -22,8 +22,9 @@ struct alignas(16) GpuView {
     int64_t pixel_offset;   // first packed pixel
     int64_t tile_offset;    // first blend tile
     int64_t tiles_x;        // blend tiles per image row
+    int64_t attr_offset;    // feature / opacity row of this view's first point
 };
-static_assert(sizeof(GpuView) == 128, "GpuView layout");
+static_assert(sizeof(GpuView) == 144, "GpuView layout");
 
 // Per view point record produced by the projection:
 //   ax, ay  fractional offsets of (u-0.5, v-0.5) from the 2x2 anchor pixel,
@@ -105,6 +106,13 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t digit, bool valid) {
 }
 
 // Feature row loads (float32 or bfloat16 storage, widened to float32).
+// float32 -> bfloat16 bits, round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return 0x7FC0u;
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }

@@ -12,14 +12,15 @@ namespace inpc {
 // One entry of the tuning table: radix digit widths of the two sorts, keys
 // per sort tile (BLOCK * items) and blend tile shape.
 struct Tuning {
-    int zdigit;       // digit bits of the per-point depth sort
-    int pdigit;       // digit bits of the per-fragment pixel sort
+    int zdigit;       // digit bits of the per-point depth sort (0: from the key width)
+    int pdigit;       // digit bits of the per-fragment pixel sort (0: from the key width)
     int sort_items;   // keys per thread in a sort tile (tile = 256 * items)
     int blend_shape;  // blend: lanes per pixel and wave tile, see blend_shape_dims()
     const char* name;
 };
 
 int tuning_count();
+int auto_digit(int key_bits);
 const Tuning& tuning(int id);
 
 // -------------------------------------------------------------- profiling
@@ -28,7 +29,7 @@ const Tuning& tuning(int id);
 enum Stage {
     kStProject, kStDepthSort, kStEmit, kStPixelSort, kStRanges, kStBlendFwd, kStClearRecords,
     kStBlendBwd, kStPointReduce, kStSortUpsweep, kStSortScan, kStSortDownsweep, kStViewGrads,
-    kNumStages
+    kStBlendWeight, kStMeanPlanes, kStAppearanceFwd, kStAppearanceBwd, kNumStages
 };
 const char* stage_name(int stage);
 void prof_begin(int stage, hipStream_t s);
@@ -85,7 +86,22 @@ struct alignas(16) PixelState {
 void launch_blend_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
-                      float* t_before, hipStream_t s);
+                      float* t_before, float* splat_weight, hipStream_t s);
+
+// Appearance step: opacity activation and degree-2 SH features per view
+// point (forward), gradient of the raw rows per point (backward).
+void launch_appearance_fwd(const float* xyz, const float* raw, const GpuView* views, int n_views,
+                           int64_t n_vp, float* opa_out, void* feat_out, bool bf16, hipStream_t s);
+void launch_appearance_bwd(const float* xyz, const float* raw, const GpuView* views, int n_views,
+                           int64_t n_points, const float* g_opa, const float* g_feat, float* grad_raw,
+                           hipStream_t s);
+
+// Per-pixel average of K planes of ``plane`` floats each (float64 sums).
+void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipStream_t s);
+
+// Per-point blend weight from the per-splat weights T alpha (indexed by splat id).
+void launch_blend_weight(int64_t n_vp, const PointRec* rec, const float* splat_weight, float* out,
+                         hipStream_t s);
 
 void launch_blend_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd(
     const int sub = __lane_id() % L;
     const uint32_t n = state[tc.q].n_blended;
     if (n == 0) return;
-    const int64_t pbase = tc.V->point_offset - tc.V->vpoint_offset;
+    const int64_t pbase = tc.V->attr_offset - tc.V->vpoint_offset;
     const uint32_t start = range[tc.q].x;
     if (rebuild_t) {
         // Same group recurrence as the forward over the blended prefix.

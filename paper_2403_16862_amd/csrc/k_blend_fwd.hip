@@ -16,11 +16,11 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ ids, const PointRec* __restrict__ rec, const FT* __restrict__ feat,
     int Fd, float tau, float* __restrict__ image, float* __restrict__ t_final,
-    PixelState* __restrict__ state, float* __restrict__ t_before) {
+    PixelState* __restrict__ state, float* __restrict__ t_before, float* __restrict__ splat_weight) {
     const TileCoord tc = tile_pixel<WXP, L>(views, n_views);
     if (!tc.inside) return;
     const int sub = __lane_id() % L;
-    const int64_t pbase = tc.V->point_offset - tc.V->vpoint_offset;
+    const int64_t pbase = tc.V->attr_offset - tc.V->vpoint_offset;
     const uint2 r = range[tc.q];
     float C[FM];
 #pragma unroll
@@ -32,8 +32,9 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
         const bool valid = i < r.y;
         float cf[FM];
         float alpha = 0.0f, om = 1.0f;
+        uint32_t id = 0;
         if (valid) {
-            const uint32_t id = ids[i];
+            id = ids[i];
             const uint32_t vp = id >> 2;
             const PointRec pr = rec[vp];
             feat_row<FT, FM, DYN>(feat, pbase + vp, Fd, cf);
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
 #pragma unroll
             for (int f = 0; f < FM; ++f) C[f] = __builtin_fmaf(ta, cf[f], C[f]);
             if (t_before) t_before[i] = g.tb;
+            if (splat_weight) splat_weight[id] = ta;
             ++nb;
         }
         T = g.t_next;
@@ -74,25 +76,27 @@ __global__ __launch_bounds__(256) void k_blend_fwd(
 template <typename FT, int FM, bool DYN, int WXP, int L>
 static void blend_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range,
                         const uint32_t* ids, const PointRec* rec, const void* feat, int Fd, float tau,
-                        float* image, float* t_final, PixelState* state, float* t_before, hipStream_t s) {
+                        float* image, float* t_final, PixelState* state, float* t_before,
+                        float* splat_weight, hipStream_t s) {
     hipLaunchKernelGGL((k_blend_fwd<FT, FM, DYN, WXP, L>), dim3((unsigned)n_tiles), dim3(256), 0, s, views,
                        n_views, range, ids, rec, reinterpret_cast<const FT*>(feat), Fd, tau, image,
-                       t_final, state, t_before);
+                       t_final, state, t_before, splat_weight);
 }
 
 void launch_blend_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views,
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
-                      float* t_before, hipStream_t s) {
+                      float* t_before, float* splat_weight, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_f(F, [&]<int FM, bool DYN>() {
         dispatch_shape(shape, [&]<int WXP, int L>() {
             if (feat_dtype == 1)
                 blend_fwd_t<__hip_bfloat16, FM, DYN, WXP, L>(views, n_views, n_tiles, range, ids, rec, feat,
-                                                             F, tau, image, t_final, state, t_before, s);
+                                                             F, tau, image, t_final, state, t_before,
+                                                             splat_weight, s);
             else
                 blend_fwd_t<float, FM, DYN, WXP, L>(views, n_views, n_tiles, range, ids, rec, feat, F, tau,
-                                                    image, t_final, state, t_before, s);
+                                                    image, t_final, state, t_before, splat_weight, s);
         });
     });
 }

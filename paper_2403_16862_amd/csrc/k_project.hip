@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
     PointRec r;
     uint32_t zb;
     project_point(V, x, y, z, r, zb);
-    r.opa = opacity[p];
+    r.opa = opacity[V.attr_offset + (vp - V.vpoint_offset)];
     rec[vp] = r;
     zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
     zval[vp] = (uint32_t)vp | (anc_mask(r.anc) << 28);

@@ -55,6 +55,87 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     grad_opa[vp] = (float)go;
 }
 
+// ------------------------------------------------ per-point blend weight
+// b[vp] = sum over the existing corners c (ascending) of w_c * T_c alpha_c:
+// the splat blend weights of Eq. 1 combined with the bilinear weights as
+// factors (Appendix A.6), the per-point quantity the probability updates of
+// Section 3.1 consume.  Splats that were not blended hold zeros (the
+// per-splat array is cleared before the forward blend).
+__global__ __launch_bounds__(256) void k_blend_weight(int64_t n_vp, const PointRec* __restrict__ rec,
+                                                      const float* __restrict__ splat_weight,
+                                                      float* __restrict__ out) {
+    const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vp >= n_vp) return;
+    const PointRec pr = rec[vp];
+    const uint32_t mask = anc_mask(pr.anc);
+    double b = 0.0;
+    if (mask != 0u) {
+        const float4 sw = reinterpret_cast<const float4*>(splat_weight)[vp];
+        const float s4[4] = {sw.x, sw.y, sw.z, sw.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!((mask >> c) & 1u)) continue;
+            float wx, wy;
+            corner_factors(pr.ax, pr.ay, c, wx, wy);
+            b = __builtin_fma((double)wx * (double)wy, (double)s4[c], b);
+        }
+    }
+    out[vp] = (float)b;
+}
+
+void launch_blend_weight(int64_t n_vp, const PointRec* rec, const float* splat_weight, float* out,
+                         hipStream_t s) {
+    if (n_vp == 0) return;
+    hipLaunchKernelGGL(k_blend_weight, dim3((unsigned)((n_vp + 255) / 256)), dim3(256), 0, s, n_vp, rec,
+                       splat_weight, out);
+}
+
+// ------------------------------------------------ multisample average
+// out[i] = (sum_k in[k * plane + i]) / K with the sum in float64 in ascending
+// k and one correctly rounded division: the per-pixel average of K feature
+// images of one view (Section 3.2, inference with several sampled clouds).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_mean_planes(const float* __restrict__ in, int K, int64_t plane,
+                                                     float* __restrict__ out) {
+    const double dk = (double)K;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if constexpr (VEC) {
+        const int64_t n4 = plane / 4;
+        const float4* src = reinterpret_cast<const float4*>(in);
+        float4* dst = reinterpret_cast<float4*>(out);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+            double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const float4 x = src[(int64_t)k * n4 + i];
+                a += (double)x.x;
+                b += (double)x.y;
+                c += (double)x.z;
+                d += (double)x.w;
+            }
+            dst[i] = make_float4((float)(a / dk), (float)(b / dk), (float)(c / dk), (float)(d / dk));
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < plane; i += stride) {
+            double a = 0.0;
+            for (int k = 0; k < K; ++k) a += (double)in[(int64_t)k * plane + i];
+            out[i] = (float)(a / dk);
+        }
+    }
+}
+
+void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipStream_t s) {
+    if (plane == 0) return;
+    const bool vec = (plane % 4) == 0 && (reinterpret_cast<uintptr_t>(in) % 16) == 0 &&
+                     (reinterpret_cast<uintptr_t>(out) % 16) == 0;
+    const int64_t items = vec ? plane / 4 : plane;
+    int64_t blocks = (items + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (vec)
+        hipLaunchKernelGGL(k_mean_planes<true>, dim3((unsigned)blocks), dim3(256), 0, s, in, K, plane, out);
+    else
+        hipLaunchKernelGGL(k_mean_planes<false>, dim3((unsigned)blocks), dim3(256), 0, s, in, K, plane, out);
+}
+
 // ------------------------------------------------ view -> point gradients
 template <int FM, bool DYN>
 __global__ __launch_bounds__(256) void k_sum_view_grads(

@@ -19,6 +19,11 @@ REL_TOL = 1e-5          # float32 image / transmittance vs the FP64 oracle
 BF16_ABS_TOL = 1e-2     # image with bfloat16 features vs FP64 on unrounded features
 GRAD_TOL = 1e-3         # gradients, relative to max(|ref|, 1e-3 rms(ref))
 BAND = 1e-4             # relative width of the termination-ambiguity band
+# Per-point blend weight: float32 T_k carries at most ~2 roundings per splat in
+# front of it (product and compensated 1 - alpha); lists end near 70-150 splats
+# at tau = 1e-4, so 2e-5 relative bounds it; values below 1e-7 are compared
+# with an absolute floor of 1e-12 (float32 spacing there).
+BW_TOL = 2e-5
 
 
 def say(*a):
@@ -110,6 +115,21 @@ def check_image(run, lists, opa, feat_for_oracle, tau, n_gpu, img_shape_pf=None,
         f"t_final rel err max {e_t.max():.3e}")
     assert e_img.max() <= tol, e_img.max()
     assert e_t.max() <= tol, e_t.max()
+    return ref
+
+
+def check_blend_weight(bw_gpu: np.ndarray, lists: oracle.Lists, opa: np.ndarray, n_gpu: np.ndarray,
+                       tol=BW_TOL):
+    """Per-point blend weights vs the oracle run with the GPU's blend counts."""
+    ref = oracle.blend_weight(lists, opa, n_gpu)
+    bw = bw_gpu.astype(np.float64)
+    err = np.abs(bw - ref)
+    rel = err / np.maximum(np.abs(ref), 1e-30)
+    ok = (rel <= tol) | (err <= 1e-12)
+    say(f"    blend weight: {int((ref > 0).sum())} points > 0, max rel err "
+        f"{rel[ref > 1e-7].max() if np.any(ref > 1e-7) else 0.0:.3e}")
+    assert np.all(ok), (int(np.argmin(ok)), bw[np.argmin(ok)], ref[np.argmin(ok)])
+    assert np.all(bw[ref == 0] == 0)
     return ref
 
 

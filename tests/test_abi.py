@@ -93,12 +93,13 @@ FAKE = 1 << 20   # never dereferenced: every call below fails validation first
 
 
 def _fwd(n=100, F=4, st=None, ws_bytes=None, saved_bytes=None, image=FAKE, feat=FAKE, saved=FAKE,
-         ws=FAKE):
+         ws=FAKE, blend_weight=None):
     c = pr.c_camera(cam())
     fws, sv, _ = pr.plain_sizes(n, cam(), F, 0, 0)
     st = st or pr.c_settings(1e-4, 0, -1)
     return pr.lib().inpc_rasterize_fwd(FAKE, feat, 0, FAKE, n, F, ctypes.byref(c), ctypes.byref(st),
-                                       image, FAKE, saved, sv if saved_bytes is None else saved_bytes,
+                                       image, FAKE, blend_weight, saved,
+                                       sv if saved_bytes is None else saved_bytes,
                                        ws, fws if ws_bytes is None else ws_bytes, None)
 
 
@@ -113,9 +114,9 @@ def test_forward_rejects_settings(st):
     assert _fwd(st=st) == -1
 
 
-def test_forward_rejects_reserved_field():
+def test_forward_rejects_unknown_flags():
     st = pr.c_settings(1e-4, 0, -1)
-    st.reserved = 1
+    st.flags = 2
     assert _fwd(st=st) == -1
 
 
@@ -124,6 +125,7 @@ def test_forward_rejects_null_and_misaligned():
     assert _fwd(image=FAKE + 4) == -1       # image must be 16-byte aligned
     assert _fwd(feat=FAKE + 8) == -1        # features must be 16-byte aligned
     assert _fwd(saved=FAKE + 16) == -1      # buffers must be 256-byte aligned
+    assert _fwd(blend_weight=FAKE + 2) == -1  # per-point blend weights are float32
 
 
 def test_batched_views_must_be_packed_in_order():
@@ -146,3 +148,22 @@ def test_view_grads_validation():
     assert rc == -1   # workspace pointer not 256-aligned
     rc = L.inpc_sum_view_grads(views, 1, 10, 4, FAKE, FAKE, FAKE, FAKE, FAKE, 8, None)
     assert rc == -2   # workspace smaller than the view table
+
+
+def test_multisample_validation():
+    c = pr.c_camera(cam())
+    off = (ctypes.c_int64 * 2)(0, 50)
+    cnt = (ctypes.c_int64 * 2)(50, 50)
+    need = ctypes.c_size_t(0)
+    L = pr.lib()
+    assert L.inpc_multisample_sizes(100, ctypes.byref(c), off, cnt, 2, 4, 0, ctypes.byref(need)) == 0
+    assert need.value > 0
+    assert L.inpc_multisample_sizes(100, ctypes.byref(c), off, cnt, 0, 4, 0, ctypes.byref(need)) == -1
+    bad = (ctypes.c_int64 * 2)(0, 60)      # second cloud runs past the point arrays
+    assert L.inpc_multisample_sizes(100, ctypes.byref(c), bad, cnt, 2, 4, 0, ctypes.byref(need)) == -1
+    st = pr.c_settings(1e-4, 1, -1)
+    args = lambda ws_bytes: (FAKE, FAKE, 0, FAKE, 100, 4, ctypes.byref(c), off, cnt, 2, ctypes.byref(st),
+                             FAKE, FAKE, FAKE, ws_bytes, None)
+    assert L.inpc_multisample_fwd(*args(need.value - 1)) == -2
+    st.mode = 7
+    assert L.inpc_multisample_fwd(*args(need.value)) == -1

@@ -8,6 +8,8 @@ benchmark times (default tuning):
   checked completely against the oracle;
 * 32M points (clusters plus a far background shell), one 1080p pose, bfloat16
   features, forward only.
+
+The first also checks the per-point blend weights of every point.
 """
 
 import numpy as np
@@ -33,7 +35,9 @@ def test_config3_full_autograd_with_fd():
     torch.cuda.synchronize()
     gf, go = f.grad.cpu().numpy(), o.grad.cpu().numpy()
     # the splat list of the same forward, via the debug hook
-    _, _, st = pr.rasterize_forward(x, f.detach(), o.detach(), s.cam, 1e-4, keep_workspace=True)
+    bw = torch.empty((s.n,), dtype=torch.float32, device=H.DEV)
+    _, _, st = pr.rasterize_forward(x, f.detach(), o.detach(), s.cam, 1e-4, keep_workspace=True,
+                                    blend_weight=bw)
     keys, ids, nb = pr.debug_fragments(st)
     L = oracle.fragments(s.xyz, s.cam)
     assert np.array_equal(keys, L.keys()) and np.array_equal(ids, L.ids)
@@ -47,6 +51,7 @@ def test_config3_full_autograd_with_fd():
     ref = oracle.blend_backward(L, s.opa, s.feat, n_gpu, s.g_img)
     H.check_grads(gf, go, ref)
     H.fd_check(L, s.opa, s.feat, n_gpu, s.g_img, None, gf, go, n_check=64, seed=3)
+    H.check_blend_weight(bw.cpu().numpy(), L, s.opa, n_gpu)
 
 
 def test_config4_batched_graph_sampled_views():
