@@ -611,3 +611,133 @@ def test_camera_centre_is_the_look_at_eye():
     eye = np.array([0.75, -0.25, -1.5])
     cam = workloads.look_at_camera(eye, [0.0, 0.0, 5.0], [0.0, -1.0, 0.0], 64, 32)
     assert np.allclose(A.camera_centre(cam), eye, atol=1e-6)
+
+
+# ------------------------------------------- octree sampling (Section 3.2, Eq. 4)
+from oracle import sampling as S   # noqa: E402
+from workloads.octree import synthetic_octree   # noqa: E402
+
+
+def test_philox_matches_numpy_bit_generator():
+    # numpy's Philox is Philox4x64-10; random_raw() yields the block of counter + 1
+    key = (0x243F6A8885A308D3, 0x13198A2E03707344)
+    for c0 in (0, 12345, (1 << 64) - 2):
+        bg = np.random.Philox(key=np.array(key, np.uint64), counter=np.array([c0, 0, 0, 0], np.uint64))
+        ref = bg.random_raw(4)
+        got = S.philox4x64(np.array([[c0 + 1 & ((1 << 64) - 1), 0, 0, 0]], np.uint64), key)[0]
+        assert np.array_equal(got, ref)
+
+
+def test_mulhi_against_python_integers():
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 2 ** 63, 1000, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    for m in (3, 2 ** 40 + 7, 2 ** 64 - 1, S.M0):
+        hi, lo = S._mulhilo(a, m)
+        for i in range(0, 1000, 97):
+            p = int(a[i]) * m
+            assert int(hi[i]) == p >> 64 and int(lo[i]) == p & (2 ** 64 - 1)
+
+
+def test_radical_inverse_matches_scipy_halton():
+    from scipy.stats import qmc
+    ref = qmc.Halton(d=3, scramble=False).random(200)       # row k is the point of index k
+    got = np.stack([S.radical_inverse(np.arange(200), b) for b in (2, 3, 5)], 1)
+    assert np.allclose(got, ref, rtol=0, atol=1e-15)
+    assert S.radical_inverse(np.array([1, 2, 3, 4]), 2).tolist() == [0.5, 0.25, 0.75, 0.125]
+
+
+def test_eq4_reweighting_closed_form():
+    # one leaf straight ahead of the canonical camera at depth 10.01, level 2:
+    # d = |10.01 - 0.01| / 100 = 0.1, factor 2^(2 * 0.5) = 2, p_hat = p / 0.2
+    cam = workloads.canonical_camera(64, 64)
+    c = np.array([[0.0, 0.0, 10.01]], np.float32)
+    ph = S.reweight_view(c, np.array([2]), np.array([0.5], np.float32), 4.0, 0.5, 1e-8, cam)
+    d = np.float32(np.abs(np.float32(10.01) - np.float32(0.01)) / np.float32(100.0))
+    assert ph[0] == np.float32(np.float32(0.5) / (d * np.float32(2.0)))
+    assert abs(float(ph[0]) - 2.5) < 1e-5
+    # the global form drops d and visibility: p / 2^(l lambda_l)
+    assert S.reweight_global(np.array([2]), np.array([0.5], np.float32), 0.5)[0] == np.float32(0.25)
+    # tau_d bounds d from below for a leaf on the near plane
+    c2 = np.array([[0.0, 0.0, 0.01]], np.float32)
+    ph2 = S.reweight_view(c2, np.array([0]), np.array([1.0], np.float32), 0.5, 0.5, 1e-8, cam)
+    assert ph2[0] == np.float32(1.0) / np.float32(1e-8)
+
+
+def test_leaf_visibility_cases():
+    cam = workloads.canonical_camera(64, 32)      # 60 deg horizontal field of view
+    cases = {
+        (0.0, 0.0, 5.0): True,       # straight ahead
+        (0.0, 0.0, -5.0): False,     # behind the camera
+        (0.0, 0.0, 0.0): True,       # contains the camera: straddles the near plane
+        (40.0, 0.0, 5.0): False,     # far right of the frustum
+        (3.5, 0.0, 5.0): True,       # x in [3.0, 4.0] at z = 5.5 reaches inside x < 0.577 z = 3.18
+        (3.9, 0.0, 5.0): False,      # x in [3.4, 4.4] stays outside for every z <= 5.5
+        (0.0, 0.0, 100.4): True,     # straddles the far plane
+        (0.0, 0.0, 101.0): False,    # beyond the far plane
+    }
+    c = np.array(list(cases), np.float32)
+    vis = S.leaf_visible(c, np.zeros(len(cases), np.int32), 1.0, cam)
+    assert vis.tolist() == list(cases.values())
+
+
+def test_integer_cdf_inverse_is_exact():
+    ph = np.array([0.0, 1.0, 3.0, 0.0, 4.0], np.float32)
+    cdf = S.integer_cdf(ph)
+    w = np.diff(np.concatenate([[0], cdf.astype(object)]))
+    assert list(w) == [0, 2 ** 35, 3 * 2 ** 35, 0, 2 ** 37]      # max 4 < 2^3: scale 2^(38-3)
+    # x spanning [0, 2^64) in equal steps hits each leaf in proportion to its weight
+    x = (np.arange(8, dtype=np.uint64) << np.uint64(61))
+    assert S.pick_leaves(cdf, x).tolist() == [1, 2, 2, 2, 4, 4, 4, 4]
+
+
+def test_multinomial_frequencies():
+    o = synthetic_octree(seed=3, level0=3, max_level=5, n_surfaces=4, root_size=4.0, origin=(0, 0, 3))
+    ph = S.reweight_global(o.level, o.prob, 0.5).astype(np.float64)
+    n = 200_000
+    blk = S.random_block(np.arange(n), 0, S.STREAM_GLOBAL, (1, 2))
+    counts = np.bincount(S.pick_leaves(S.integer_cdf(ph.astype(np.float32)), blk[:, 0]), minlength=o.n)
+    expect = n * ph / ph.sum()
+    chi2 = np.sum((counts - expect) ** 2 / np.maximum(expect, 1e-9))
+    assert chi2 < o.n + 6 * np.sqrt(2 * o.n)          # chi-square with ~L degrees of freedom
+
+
+def test_view_samples_lie_in_their_leaves_and_the_frustum():
+    o = synthetic_octree(seed=4, level0=3, max_level=5, n_surfaces=4, root_size=4.0, origin=(0, 0, 3))
+    cam = workloads.look_at_camera([0.3, -0.2, -1.0], [0, 0, 3], [0, -1, 0], 96, 64)
+    xyz, leaf, unresolved = S.sample_view(o.centre, o.level, o.prob, o.root_size, 0.5, 1e-8, cam, 20_000,
+                                          (5, 6), max_rounds=64)
+    assert unresolved == 0 and np.all(S.point_visible(xyz, cam))
+    half = S.edge(o.root_size, o.level[leaf]) / 2
+    assert np.all(np.abs(xyz - o.centre[leaf]) <= half[:, None] * (1 + 1e-6))
+    vis = S.leaf_visible(o.centre, o.level, o.root_size, cam)
+    assert np.all(vis[leaf])
+    # the index form recomputes the same samples
+    sub = np.array([0, 17, 19_999])
+    x2, l2, _ = S.sample_view(o.centre, o.level, o.prob, o.root_size, 0.5, 1e-8, cam, 20_000, (5, 6), 64,
+                              index=sub)
+    assert np.array_equal(x2, xyz[sub]) and np.array_equal(l2, leaf[sub])
+    # without re-sampling some samples of partly visible leaves fall outside
+    x3, _, _ = S.sample_view(o.centre, o.level, o.prob, o.root_size, 0.5, 1e-8, cam, 20_000, (5, 6), 0)
+    assert not np.all(S.point_visible(x3, cam))
+
+
+def test_global_extraction_counts_and_halton_positions():
+    from scipy.stats import qmc
+    o = synthetic_octree(seed=5, level0=2, max_level=3, n_surfaces=2, root_size=2.0, origin=(0, 0, 3))
+    xyz, leaf, counts = S.sample_global(o.centre, o.level, o.prob, o.root_size, 0.5, 5000, (9, 9))
+    assert counts.sum() == 5000 and np.all(np.diff(leaf) >= 0)
+    i = int(np.argmax(counts))
+    rows = xyz[leaf == i]
+    h = qmc.Halton(d=3, scramble=False).random(counts[i] + 1)[1:]
+    e = S.edge(o.root_size, o.level[i:i + 1])[0]
+    assert np.allclose(rows, o.centre[i] + (h - 0.5) * e, atol=1e-6)
+
+
+def test_probability_update_eq2_eq3():
+    leaf = np.array([0, 0, 2, 0])
+    b = np.array([0.25, 0.75, 0.5, 0.125], np.float32)
+    p, q = S.update_probabilities(leaf, b, 4, 0.5, np.array([1.0, 0.5, 0.25, 0.125], np.float32),
+                                  np.array([0.5, 0.5, 0.5, 1.0], np.float32))
+    # leaf 0: max(0.5, 0.75) and max(0.25, 0.75 - 0.125); leaf 1 and 3 decay; leaf 2: max(0.125, 0.5), max(0.25, 0)
+    assert p.tolist() == [0.75, 0.25, 0.5, 0.0625]
+    assert q.tolist() == [0.625, 0.25, 0.25, 0.5]
