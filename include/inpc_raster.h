@@ -198,6 +198,60 @@ int inpc_appearance_bwd(const float *xyz, const float *raw, int64_t n_points,
                         const float *grad_opacity, const float *grad_feat, float *grad_raw,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* -------------------------------------------------------- octree sampling */
+
+/* Point sampling from the probability octree (Section 3.2, Eq. 4; Appendix
+ * A.4) and the per-leaf probability updates (Section 3.1, Eq. 2, Eq. 3).
+ * The octree is given by its leaves: centre [L,3] f32 (world), level [L]
+ * int32 (0..31; edge = root_size * 2^-level), prob [L] f32 in [0,1].
+ * 1 <= L <= 2^24 (the paper caps the octree at 256^3 leaves).
+ *
+ * Re-weighting (Eq. 4): p_hat = 1_visible * p / (d * 2^(level*lambda_l)),
+ * d = max(|z_view(centre) - near| / far, tau_d) (Appendix A.4); a leaf is
+ * visible unless its cube lies entirely outside one of the six frustum
+ * half-spaces (near, far, u = 0, u = W, v = 0, v = H).  The global
+ * extraction omits 1_visible and d.  All in float32, in a fixed order.
+ * Multinomial sampling with replacement inverts the integer CDF of
+ * w = floor(p_hat * 2^(38 - e)) (m = max p_hat < 2^e): the leaf of a 64-bit
+ * random x is the first i with CDF_i > floor(x * W_total / 2^64).
+ * Random numbers: Philox4x64-10 with key (seed0, seed1) and counter
+ * (sample, round, stream, 0), stream 1 here (word 0: leaf, top 24 bits of
+ * words 1..3: position fractions f), stream 2 for the global extraction.
+ * Position = centre + (f - 0.5) * edge per axis (float32).
+ *
+ * inpc_sample_view: n_samples viewpoint-specific samples, xyz [n,3] f32 and
+ * leaf_index [n] int32 in sample order.  A sample outside the image
+ * frustum (not near < z < far, 0 <= u < W, 0 <= v < H) is drawn again with
+ * the next round, at most max_rounds times (Appendix A.4); max_rounds = 0
+ * keeps every first draw (inference with multisampling).  *n_unresolved
+ * (device int64) receives the number of samples still outside after
+ * max_rounds.  If no leaf is visible every sample is unresolved, with NaN
+ * positions and leaf -1.
+ * inpc_sample_global: viewpoint-independent extraction; the multinomial
+ * draws give per-leaf counts, outputs are ordered by leaf, and the j-th
+ * sample of a leaf sits at the 3D Halton point of index j+1 (bases 2, 3, 5)
+ * inside the leaf.
+ * inpc_update_probabilities: for each leaf with points (leaf_index[i] =
+ * leaf; out-of-range indices are ignored), p = max(lambda_u * p, max b) and
+ * q = max(lambda_u * q, max b - min b) over its points' blend weights b
+ * (the per-point output of inpc_rasterize_fwd); leaves without points decay:
+ * p = lambda_u * p, q = lambda_u * q.  prob and subdiv [L] are updated in
+ * place.  Deterministic (integer atomics on order-preserving keys).
+ * ws: inpc_sampling_sizes() bytes of device scratch, 256-byte aligned. */
+int inpc_sampling_sizes(int64_t n_leaves, size_t *ws_bytes);
+int inpc_sample_view(const float *centre, const int32_t *level, const float *prob, int64_t n_leaves,
+                     float root_size, float lambda_l, float tau_d, const inpc_camera_t *cam_host,
+                     int64_t n_samples, uint64_t seed0, uint64_t seed1, int32_t max_rounds,
+                     float *xyz, int32_t *leaf_index, int64_t *n_unresolved, void *ws,
+                     size_t ws_bytes, void *stream);
+int inpc_sample_global(const float *centre, const int32_t *level, const float *prob,
+                       int64_t n_leaves, float root_size, float lambda_l, int64_t n_samples,
+                       uint64_t seed0, uint64_t seed1, float *xyz, int32_t *leaf_index, void *ws,
+                       size_t ws_bytes, void *stream);
+int inpc_update_probabilities(const int32_t *leaf_index, const float *blend_weight,
+                              int64_t n_points, int64_t n_leaves, float lambda_u, float *prob,
+                              float *subdiv, void *ws, size_t ws_bytes, void *stream);
+
 /* --------------------------------------------------------- multisampling */
 
 /* Multisampled inference (Section 3.2: for one viewpoint, several point

@@ -86,6 +86,12 @@ def lib():
         "inpc_sum_view_grads": [view_p, i32, i64, i32, P, P, P, P, P, sz, P],
         "inpc_multisample_sizes": [i64, cam_p, P, P, i32, i32, i32, szp],
         "inpc_appearance_fwd": [P, P, i64, view_p, i32, P, P, i32, P, sz, P],
+        "inpc_sampling_sizes": [i64, szp],
+        "inpc_sample_view": [P, P, P, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float, cam_p, i64,
+                             ctypes.c_uint64, ctypes.c_uint64, i32, P, P, P, P, sz, P],
+        "inpc_sample_global": [P, P, P, i64, ctypes.c_float, ctypes.c_float, i64, ctypes.c_uint64,
+                               ctypes.c_uint64, P, P, P, sz, P],
+        "inpc_update_probabilities": [P, P, i64, i64, ctypes.c_float, P, P, P, sz, P],
         "inpc_appearance_bwd": [P, P, i64, view_p, i32, P, P, P, P, sz, P],
         "inpc_multisample_fwd": [P, P, i32, P, i64, i32, cam_p, P, P, i32, set_p, P, P, P, sz, P],
         "inpc_tuning_count": [],
@@ -505,6 +511,60 @@ def render_sh(xyz, raw, views, t_threshold: float = 1e-4, mode="save", tuning_id
     if xyz.dtype != torch.float32 or not xyz.is_cuda:
         raise TypeError("xyz must be a float32 device tensor")
     return _ShRaster.apply(xyz.contiguous(), raw.contiguous(), views, t_threshold, mode, tuning_id, feat_dtype)
+
+
+# ---------------------------------------------------------------- octree sampling
+class OctreeLeaves:
+    """Device arrays of a probability octree's leaves (centre [L,3] f32, level [L] int32,
+    prob [L] f32, subdiv [L] f32) and the edge length of a level-0 cube."""
+
+    def __init__(self, centre, level, prob, subdiv, root_size: float):
+        self.centre = centre.contiguous().float()
+        self.level = level.contiguous().to(torch.int32)
+        self.prob = prob.contiguous().float()
+        self.subdiv = subdiv.contiguous().float()
+        self.root_size = float(root_size)
+        self.n = int(self.level.shape[0])
+        need = ctypes.c_size_t(0)
+        _check(lib().inpc_sampling_sizes(self.n, ctypes.byref(need)), "inpc_sampling_sizes")
+        self.ws = _buffer(need.value, self.centre.device)
+
+
+def sample_view(tree: OctreeLeaves, cam, n_samples: int, seed=(0, 0), lambda_l: float = 0.5,
+                tau_d: float = 1e-8, max_rounds: int = 64):
+    """Viewpoint-specific samples -> (xyz [n,3], leaf [n] int32, unresolved count tensor [1] int64)."""
+    dev = tree.centre.device
+    xyz = torch.empty((n_samples, 3), dtype=torch.float32, device=dev)
+    leaf = torch.empty((n_samples,), dtype=torch.int32, device=dev)
+    unres = torch.empty((1,), dtype=torch.int64, device=dev)
+    c = c_camera(cam)
+    _check(lib().inpc_sample_view(_ptr(tree.centre), _ptr(tree.level), _ptr(tree.prob), tree.n, tree.root_size,
+                                  float(lambda_l), float(tau_d), ctypes.byref(c), int(n_samples),
+                                  int(seed[0]), int(seed[1]), int(max_rounds), _ptr(xyz), _ptr(leaf), _ptr(unres),
+                                  _ptr(tree.ws), tree.ws.numel(), _stream()), "inpc_sample_view")
+    return xyz, leaf, unres
+
+
+def sample_global(tree: OctreeLeaves, n_samples: int, seed=(0, 0), lambda_l: float = 0.5):
+    """Viewpoint-independent extraction -> (xyz [n,3] ordered by leaf, leaf [n] int32)."""
+    dev = tree.centre.device
+    xyz = torch.empty((n_samples, 3), dtype=torch.float32, device=dev)
+    leaf = torch.empty((n_samples,), dtype=torch.int32, device=dev)
+    _check(lib().inpc_sample_global(_ptr(tree.centre), _ptr(tree.level), _ptr(tree.prob), tree.n, tree.root_size,
+                                    float(lambda_l), int(n_samples), int(seed[0]), int(seed[1]), _ptr(xyz),
+                                    _ptr(leaf), _ptr(tree.ws), tree.ws.numel(), _stream()), "inpc_sample_global")
+    return xyz, leaf
+
+
+def update_probabilities(tree: OctreeLeaves, leaf, blend_weight, lambda_u: float = 0.9968):
+    """Eq. 2 and Eq. 3 on tree.prob / tree.subdiv in place, from per-point leaves and blend weights."""
+    leaf = leaf.contiguous().to(torch.int32)
+    bw = blend_weight.contiguous().float()
+    if leaf.numel() != bw.numel():
+        raise ValueError("one leaf index per blend weight")
+    _check(lib().inpc_update_probabilities(_ptr(leaf), _ptr(bw), int(leaf.numel()), tree.n, float(lambda_u),
+                                           _ptr(tree.prob), _ptr(tree.subdiv), _ptr(tree.ws), tree.ws.numel(),
+                                           _stream()), "inpc_update_probabilities")
 
 
 # ---------------------------------------------------------------- multisampling

@@ -8,12 +8,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinpc_raster.so")
 SOURCES = ["k_project.hip", "k_sort.hip", "k_blend_fwd.hip", "k_blend_bwd.hip", "k_reduce.hip",
-           "k_appearance.hip", "api.cpp"]
+           "k_appearance.hip", "k_sampling.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-Wall",
-    # packed-FP32 instructions stay off (see the build notes in the design doc)
+    # no packed-FP32 instruction generation: every float operation stays scalar
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-gpu-rdc",
 ]

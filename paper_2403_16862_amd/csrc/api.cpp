@@ -249,7 +249,8 @@ static T* at(void* base, size_t off) {
 static const char* kStageNames[kNumStages] = {
     "project", "depth_sort", "emit", "pixel_sort", "ranges", "blend_fwd", "clear_records",
     "blend_bwd", "point_reduce", "sort_upsweep", "sort_scan", "sort_downsweep", "view_grads",
-    "blend_weight", "mean_planes", "appearance_fwd", "appearance_bwd"};
+    "blend_weight", "mean_planes", "appearance_fwd", "appearance_bwd", "sample_weights", "sample_draw",
+    "prob_update"};
 
 const char* stage_name(int st) { return (st >= 0 && st < kNumStages) ? kStageNames[st] : ""; }
 
@@ -789,6 +790,51 @@ int inpc_appearance_bwd(const float* xyz, const float* raw, int64_t n_points, co
     return check_launch("inpc_appearance_bwd");
 }
 
+// ------------------------------------------------------------ sampling
+struct SampleLayout {
+    size_t scalars, phat, cdf, tiles, counts, count_cdf, total;
+};
+
+static SampleLayout sample_layout(int64_t n_leaves) {
+    SampleLayout l;
+    Carver c;
+    const size_t L = (size_t)n_leaves, T = (L + 2047) / 2048 + 1;
+    l.scalars = c.take(256);
+    l.phat = c.take(4 * L);
+    l.cdf = c.take(8 * L);
+    l.tiles = c.take(8 * T);
+    l.counts = c.take(4 * L);
+    l.count_cdf = c.take(8 * L);
+    l.total = c.off;
+    return l;
+}
+
+static int check_octree(const float* centre, const int32_t* level, const float* prob, int64_t n_leaves,
+                        float root_size, float lambda_l) {
+    if (n_leaves < 1) return INPC_EINVAL;
+    if (n_leaves > ((int64_t)1 << 24)) return INPC_EUNSUPPORTED;
+    if (!centre || !level || !prob || !aligned(centre, 4) || !aligned(level, 4) || !aligned(prob, 4))
+        return INPC_EINVAL;
+    if (!std::isfinite(root_size) || !(root_size > 0.0f) || !std::isfinite(lambda_l)) return INPC_EINVAL;
+    return INPC_OK;
+}
+
+static LevelTable level_table(float lambda_l) {
+    LevelTable t;
+    for (int l = 0; l < 32; ++l) t.f[l] = (float)std::pow(2.0, (double)l * (double)lambda_l);
+    return t;
+}
+
+static SampleCam sample_cam(const inpc_camera_t& c) {
+    SampleCam s;
+    std::memcpy(s.R, c.R, sizeof s.R);
+    std::memcpy(s.t, c.t, sizeof s.t);
+    s.fx = c.fx; s.fy = c.fy; s.cx = c.cx; s.cy = c.cy;
+    s.near_p = c.near_plane; s.far_p = c.far_plane;
+    s.W = c.width; s.H = c.height;
+    return s;
+}
+
 int inpc_multisample_sizes(int64_t n_points, const inpc_camera_t* cam, const int64_t* cloud_offset,
                            const int64_t* cloud_count, int32_t n_clouds, int32_t F, int32_t fdt,
                            size_t* ws_bytes) {
@@ -803,6 +849,99 @@ int inpc_multisample_fwd(const float* xyz, const void* feat, int32_t fdt, const 
                          float* image, float* t_final, void* ws, size_t ws_bytes, void* stream) {
     return ms_impl(xyz, feat, fdt, opa, n_points, F, cam, cloud_offset, cloud_count, n_clouds, st, image,
                    t_final, ws, ws_bytes, nullptr, stream);
+}
+
+int inpc_sampling_sizes(int64_t n_leaves, size_t* ws_bytes) {
+    if (!ws_bytes || n_leaves < 1) return INPC_EINVAL;
+    if (n_leaves > ((int64_t)1 << 24)) return INPC_EUNSUPPORTED;
+    *ws_bytes = sample_layout(n_leaves).total;
+    return INPC_OK;
+}
+
+int inpc_sample_view(const float* centre, const int32_t* level, const float* prob, int64_t n_leaves,
+                     float root_size, float lambda_l, float tau_d, const inpc_camera_t* cam, int64_t n_samples,
+                     uint64_t seed0, uint64_t seed1, int32_t max_rounds, float* xyz, int32_t* leaf_index,
+                     int64_t* n_unresolved, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_octree(centre, level, prob, n_leaves, root_size, lambda_l);
+    if (rc) return rc;
+    if (!cam) return INPC_EINVAL;
+    rc = check_camera(*cam);
+    if (rc) return rc;
+    if (!std::isfinite(tau_d) || !(tau_d > 0.0f)) return INPC_EINVAL;
+    if (n_samples < 0 || n_samples >= ((int64_t)1 << 31) || max_rounds < 0 || max_rounds > 65536)
+        return INPC_EINVAL;
+    if (!n_unresolved || !aligned(n_unresolved, 8)) return INPC_EINVAL;
+    if (n_samples > 0 && (!xyz || !leaf_index || !aligned(xyz, 4) || !aligned(leaf_index, 4)))
+        return INPC_EINVAL;
+    if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
+    const SampleLayout l = sample_layout(n_leaves);
+    if (ws_bytes < l.total) return INPC_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const SampleCam sc = sample_cam(*cam);
+    {
+        ProfScope p(kStSampleWeights, s);
+        launch_sample_weights(centre, level, prob, n_leaves, root_size, tau_d, level_table(lambda_l), sc, true,
+                              at<float>(ws, l.phat), at<uint32_t>(ws, l.scalars), at<uint64_t>(ws, l.tiles),
+                              at<uint64_t>(ws, l.cdf), s);
+    }
+    {
+        ProfScope p(kStSampleDraw, s);
+        launch_sample_view(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, sc, seed0, seed1,
+                           n_samples, max_rounds, xyz, leaf_index,
+                           reinterpret_cast<unsigned long long*>(n_unresolved), s);
+    }
+    return check_launch("inpc_sample_view");
+}
+
+int inpc_sample_global(const float* centre, const int32_t* level, const float* prob, int64_t n_leaves,
+                       float root_size, float lambda_l, int64_t n_samples, uint64_t seed0, uint64_t seed1,
+                       float* xyz, int32_t* leaf_index, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_octree(centre, level, prob, n_leaves, root_size, lambda_l);
+    if (rc) return rc;
+    if (n_samples < 0 || n_samples >= ((int64_t)1 << 31)) return INPC_EINVAL;
+    if (n_samples > 0 && (!xyz || !leaf_index || !aligned(xyz, 4) || !aligned(leaf_index, 4)))
+        return INPC_EINVAL;
+    if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
+    const SampleLayout l = sample_layout(n_leaves);
+    if (ws_bytes < l.total) return INPC_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    inpc_camera_t dummy{};
+    const SampleCam sc = sample_cam(dummy);
+    {
+        ProfScope p(kStSampleWeights, s);
+        launch_sample_weights(centre, level, prob, n_leaves, root_size, 1.0f, level_table(lambda_l), sc, false,
+                              at<float>(ws, l.phat), at<uint32_t>(ws, l.scalars), at<uint64_t>(ws, l.tiles),
+                              at<uint64_t>(ws, l.cdf), s);
+    }
+    {
+        ProfScope p(kStSampleDraw, s);
+        launch_sample_global(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, seed0, seed1,
+                             n_samples, at<uint32_t>(ws, l.counts), at<uint64_t>(ws, l.tiles),
+                             at<uint64_t>(ws, l.count_cdf), xyz, leaf_index, s);
+    }
+    return check_launch("inpc_sample_global");
+}
+
+int inpc_update_probabilities(const int32_t* leaf_index, const float* blend_weight, int64_t n_points,
+                              int64_t n_leaves, float lambda_u, float* prob, float* subdiv, void* ws,
+                              size_t ws_bytes, void* stream) {
+    if (n_leaves < 1 || n_points < 0) return INPC_EINVAL;
+    if (n_leaves > ((int64_t)1 << 24)) return INPC_EUNSUPPORTED;
+    if (!std::isfinite(lambda_u)) return INPC_EINVAL;
+    if (!prob || !subdiv || !aligned(prob, 4) || !aligned(subdiv, 4)) return INPC_EINVAL;
+    if (n_points > 0 && (!leaf_index || !blend_weight || !aligned(leaf_index, 4) || !aligned(blend_weight, 4)))
+        return INPC_EINVAL;
+    if (!ws || !aligned(ws, 256)) return INPC_EINVAL;
+    if (ws_bytes < sample_layout(n_leaves).total) return INPC_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carver c;
+    const size_t kmax = c.take(4 * (size_t)n_leaves), kmin = c.take(4 * (size_t)n_leaves);
+    {
+        ProfScope p(kStProbUpdate, s);
+        launch_prob_update(leaf_index, blend_weight, n_points, n_leaves, lambda_u, prob, subdiv,
+                           at<uint32_t>(ws, kmax), at<uint32_t>(ws, kmin), s);
+    }
+    return check_launch("inpc_update_probabilities");
 }
 
 int inpc_tuning_count(void) { return kNumTunings; }

@@ -29,7 +29,8 @@ const Tuning& tuning(int id);
 enum Stage {
     kStProject, kStDepthSort, kStEmit, kStPixelSort, kStRanges, kStBlendFwd, kStClearRecords,
     kStBlendBwd, kStPointReduce, kStSortUpsweep, kStSortScan, kStSortDownsweep, kStViewGrads,
-    kStBlendWeight, kStMeanPlanes, kStAppearanceFwd, kStAppearanceBwd, kNumStages
+    kStBlendWeight, kStMeanPlanes, kStAppearanceFwd, kStAppearanceBwd, kStSampleWeights, kStSampleDraw,
+    kStProbUpdate, kNumStages
 };
 const char* stage_name(int stage);
 void prof_begin(int stage, hipStream_t s);
@@ -87,6 +88,28 @@ void launch_blend_fwd(int F, int feat_dtype, int shape, const GpuView* views, in
                       int64_t n_tiles, const uint2* range, const uint32_t* ids, const PointRec* rec,
                       const void* feat, float tau, float* image, float* t_final, PixelState* state,
                       float* t_before, float* splat_weight, hipStream_t s);
+
+// Octree sampling (Eq. 4) and probability updates (Eq. 2, Eq. 3).
+struct SampleCam {
+    float R[9], t[3];
+    float fx, fy, cx, cy, near_p, far_p;
+    int32_t W, H;
+};
+struct LevelTable {
+    float f[32];   // 2^(l * lambda_l) rounded to float32, l = 0..31
+};
+void launch_sample_weights(const float* centre, const int32_t* level, const float* prob, int64_t n_leaves,
+                           float root, float tau_d, const LevelTable& lt, const SampleCam& cam, bool view,
+                           float* phat, uint32_t* max_bits, uint64_t* tile_sum, uint64_t* cdf, hipStream_t s);
+void launch_sample_view(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
+                        int64_t n_leaves, const SampleCam& cam, uint64_t seed0, uint64_t seed1, int64_t n,
+                        int max_rounds, float* xyz, int32_t* leaf, unsigned long long* unresolved,
+                        hipStream_t s);
+void launch_sample_global(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
+                          int64_t n_leaves, uint64_t seed0, uint64_t seed1, int64_t n, uint32_t* counts,
+                          uint64_t* tile_sum, uint64_t* count_cdf, float* xyz, int32_t* leaf, hipStream_t s);
+void launch_prob_update(const int32_t* leaf, const float* b, int64_t n, int64_t n_leaves, float lambda_u,
+                        float* prob, float* subdiv, uint32_t* kmax, uint32_t* kmin, hipStream_t s);
 
 // Appearance step: opacity activation and degree-2 SH features per view
 // point (forward), gradient of the raw rows per point (backward).

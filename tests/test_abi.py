@@ -167,3 +167,26 @@ def test_multisample_validation():
     assert L.inpc_multisample_fwd(*args(need.value - 1)) == -2
     st.mode = 7
     assert L.inpc_multisample_fwd(*args(need.value)) == -1
+
+
+def test_sampling_validation():
+    L = pr.lib()
+    need = ctypes.c_size_t(0)
+    assert L.inpc_sampling_sizes(0, ctypes.byref(need)) == -1
+    assert L.inpc_sampling_sizes((1 << 24) + 1, ctypes.byref(need)) == -3
+    assert L.inpc_sampling_sizes(1000, ctypes.byref(need)) == 0 and need.value >= 1000 * 24
+    c = pr.c_camera(cam())
+    unres = FAKE + 64
+
+    def view(n_leaves=1000, tau_d=1e-8, rounds=8, ws_bytes=None, n=10):
+        return L.inpc_sample_view(FAKE, FAKE, FAKE, n_leaves, 16.0, 0.5, tau_d, ctypes.byref(c), n, 1, 2, rounds,
+                                  FAKE, FAKE, unres, FAKE, need.value if ws_bytes is None else ws_bytes, None)
+    assert view(ws_bytes=need.value - 1) == -2
+    assert view(tau_d=0.0) == -1
+    assert view(rounds=-1) == -1
+    assert view(n=-5) == -1
+    assert view(n_leaves=0) == -1
+    assert L.inpc_sample_global(FAKE, FAKE, FAKE, 1000, -1.0, 0.5, 10, 1, 2, FAKE, FAKE, FAKE, need.value,
+                                None) == -1     # root size must be positive
+    assert L.inpc_update_probabilities(FAKE, FAKE, 10, 1000, 0.9968, FAKE, FAKE, FAKE, need.value - 1,
+                                       None) == -2
