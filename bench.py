@@ -6,9 +6,11 @@ second (fragments = splats the forward emits).  Also reported on the same
 JSON line: per-stage timings measured with HIP events inside the timed
 steps, the roofline figure of the dominant kernel, the CPU oracle's rate on
 the same workload, and the batched bfloat16 path (16 views of uneven size,
-one HIP-graph replay) against 16 sequential float32 plain calls.
+one HIP-graph replay) against 16 sequential float32 plain calls, and the
+steps around the rasterizer (octree sampling, the appearance step, the
+per-point blend weight, multisampled inference, the probability update).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu] [--no-next]
 """
 
 import argparse
@@ -34,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the timings of sampling, appearance, blend weight and multisampling")
     ap.add_argument("--tuning", type=int, default=-1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
@@ -210,8 +214,23 @@ def main():
         }
         del L, fw
 
+    if not args.no_next:
+        # cost of the optional per-point blend weight output on the same forward
+        bw = torch.empty((s.n,), dtype=torch.float32, device=dev)
+
+        def fwd(with_bw):
+            pr.rasterize_forward(x, f.detach(), o.detach(), s.cam, 1e-4, "save", args.tuning,
+                                 blend_weight=bw if with_bw else None)
+        result["blend_weight"] = {
+            "ms_forward_without": round(time_ms(torch, lambda: fwd(False)), 4),
+            "ms_forward_with": round(time_ms(torch, lambda: fwd(True)), 4),
+        }
+
     if not args.no_batched:
         result["batched"] = bench_batched(pr, torch, np, workloads, log)
+
+    if not args.no_next:
+        result["pipeline"] = bench_pipeline(pr, torch, np, workloads, log)
 
     if args.calib_copy:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -221,6 +240,104 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 1 GiB read + 1 GiB written")
     print(json.dumps(result), flush=True)
+
+
+def time_ms(torch, fn, reps=10, warm=2):
+    """Mean time of fn() over reps calls, HIP events on the current stream."""
+    for _ in range(warm):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_pipeline(pr, torch, np, workloads, log):
+    """The data-parallel steps around the rasterizer, at the paper's sizes:
+    8M viewpoint-specific samples from a 634k-leaf octree (training), the
+    appearance step (opacity activation + degree-2 SH, 37 raw floats per
+    point -> 4-D feature), rasterization with per-point blend weights, its
+    backward through the appearance step, the probability update; and
+    inference: 4 clouds of 8M samples without re-sampling, appearance, and
+    the multisampled average, 1920x1080."""
+    from workloads.octree import synthetic_octree
+    dev = "cuda:0"
+    t0 = time.time()
+    o = synthetic_octree()
+    log(f"generated octree in {time.time() - t0:.1f}s: {o.n} leaves")
+    tree = pr.OctreeLeaves(torch.from_numpy(o.centre).to(dev), torch.from_numpy(o.level).to(dev),
+                           torch.from_numpy(o.prob).to(dev), torch.from_numpy(o.subdiv).to(dev), o.root_size)
+    cam = workloads.look_at_camera([0.3, -0.2, -2.0], [0.0, 0.0, 6.0], [0.0, -1.0, 0.0], 1920, 1080)
+    n, K = 8_000_000, 4
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1234)
+
+    def raw_rows(m):
+        # same recipe as workloads.sh_raw, drawn on the device
+        r = torch.empty((m, 37), dtype=torch.float32, device=dev)
+        r[:, 0].normal_(-0.5, 1.5, generator=gen)
+        r[:, 1:5].uniform_(0.0, 2.0, generator=gen)
+        r[:, 5:].normal_(0.0, 0.3, generator=gen)
+        return r
+
+    out = {"leaves": o.n, "samples": n, "width": cam.width, "height": cam.height}
+    # --- training-style step
+    xyz, leaf, unres = pr.sample_view(tree, cam, n, seed=(1, 2), max_rounds=64)
+    out["ms_sample_view_8M"] = round(time_ms(torch, lambda: pr.sample_view(tree, cam, n, seed=(1, 2))), 4)
+    out["unresolved"] = int(unres.item())
+    raw = raw_rows(n).requires_grad_(True)
+    views = pr.make_views([cam], [0], [n])
+    out["ms_appearance_fwd_8M"] = round(time_ms(torch, lambda: pr.appearance_forward(xyz, raw.detach(), views)), 4)
+    go = torch.randn((n,), device=dev, generator=gen)
+    gf = torch.randn((n, 4), device=dev, generator=gen)
+    out["ms_appearance_bwd_8M"] = round(
+        time_ms(torch, lambda: pr.appearance_backward(xyz, raw.detach(), views, go, gf)), 4)
+    # appearance bytes: fwd reads xyz + raw rows, writes opacity + feature; bwd reads
+    # xyz, the logit, both gradients and writes the raw gradient
+    ab_f, ab_b = n * (12 + 148 + 4 + 16), n * (12 + 4 + 4 + 16 + 148)
+    out["appearance_gbs"] = {"fwd": round(ab_f / out["ms_appearance_fwd_8M"] / 1e6, 1),
+                             "bwd": round(ab_b / out["ms_appearance_bwd_8M"] / 1e6, 1)}
+    g_img = torch.randn((cam.height * cam.width, 4), device=dev, generator=gen)
+    bw = torch.empty((n,), dtype=torch.float32, device=dev)
+
+    def train_step():
+        xs, lf, _ = pr.sample_view(tree, cam, n, seed=(1, 2))
+        raw.grad = None
+        img, tf = pr.render_sh(xs, raw, views, blend_weight=bw)
+        torch.autograd.backward([img], [g_img])
+        pr.update_probabilities(tree, lf, bw)
+    out["ms_train_step"] = round(time_ms(torch, train_step, reps=5), 4)
+    out["ms_prob_update"] = round(time_ms(torch, lambda: pr.update_probabilities(tree, leaf, bw)), 4)
+    # --- inference: 4 x 8M without re-sampling, multisampled average
+    xs4 = torch.empty((K * n, 3), dtype=torch.float32, device=dev)
+    lf4 = torch.empty((K * n,), dtype=torch.int32, device=dev)
+
+    def sample4():
+        for k in range(K):
+            xk, lk, _ = pr.sample_view(tree, cam, n, seed=(100 + k, 2), max_rounds=0)
+            xs4[k * n:(k + 1) * n] = xk
+            lf4[k * n:(k + 1) * n] = lk
+    sample4()
+    raw4 = raw_rows(K * n)
+    views4 = pr.make_views([cam] * K, [k * n for k in range(K)], [n] * K)
+    out["ms_sample_4x8M"] = round(time_ms(torch, sample4, reps=3), 4)
+    out["ms_appearance_4x8M"] = round(time_ms(torch, lambda: pr.appearance_forward(xs4, raw4, views4), reps=3), 4)
+    o4, f4 = pr.appearance_forward(xs4, raw4, views4)
+    offs = [k * n for k in range(K)]
+    out["ms_multisample_raster_4x8M"] = round(
+        time_ms(torch, lambda: pr.multisample(xs4, f4, o4, cam, offs, [n] * K), reps=3), 4)
+
+    def infer():
+        sample4()
+        a_o, a_f = pr.appearance_forward(xs4, raw4, views4)
+        pr.multisample(xs4, a_f, a_o, cam, offs, [n] * K)
+    out["ms_inference_4x8M"] = round(time_ms(torch, infer, reps=3), 4)
+    log(f"pipeline: {json.dumps(out)}")
+    return out
 
 
 def bench_batched(pr, torch, np, workloads, log, reps=5):

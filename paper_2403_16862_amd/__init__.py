@@ -480,10 +480,10 @@ class _ShRaster(torch.autograd.Function):
     bfloat16."""
 
     @staticmethod
-    def forward(ctx, xyz, raw, views, t_threshold, mode, tuning_id, feat_dtype):
+    def forward(ctx, xyz, raw, views, t_threshold, mode, tuning_id, feat_dtype, blend_weight):
         opa, feat = appearance_forward(xyz, raw, views, feat_dtype)
         image, t_final, state = _forward(xyz, feat, opa, views, len(views), t_threshold, mode, tuning_id,
-                                         False, None, None, ATTR_PER_VIEW_POINT)
+                                         False, None, blend_weight, ATTR_PER_VIEW_POINT)
         ctx.state = state
         ctx.views = views
         ctx.save_for_backward(xyz, raw, feat, opa)
@@ -494,23 +494,26 @@ class _ShRaster(torch.autograd.Function):
     def backward(ctx, g_img, g_t):
         xyz, raw, feat, opa = ctx.saved_tensors
         if g_img is None and g_t is None:
-            return (None,) * 7
+            return (None,) * 8
         st = ctx.state
         if g_img is None:
             P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
             g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
         gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
-        return None, appearance_backward(xyz, raw, ctx.views, go, gf), None, None, None, None, None
+        return None, appearance_backward(xyz, raw, ctx.views, go, gf), None, None, None, None, None, None
 
 
 def render_sh(xyz, raw, views, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1,
-              feat_dtype=torch.float32):
+              feat_dtype=torch.float32, blend_weight=None):
     """Appearance step (opacity activation + degree-2 SH, per view point) then
     batched rasterization -> packed (image [sum P, 4], t_final [sum P]);
-    differentiable with respect to ``raw`` [N, 37]."""
+    differentiable with respect to ``raw`` [N, 37].  ``blend_weight``: optional
+    float32 tensor (one entry per view point) that receives the per-point
+    blend weights of the forward."""
     if xyz.dtype != torch.float32 or not xyz.is_cuda:
         raise TypeError("xyz must be a float32 device tensor")
-    return _ShRaster.apply(xyz.contiguous(), raw.contiguous(), views, t_threshold, mode, tuning_id, feat_dtype)
+    return _ShRaster.apply(xyz.contiguous(), raw.contiguous(), views, t_threshold, mode, tuning_id, feat_dtype,
+                           blend_weight)
 
 
 # ---------------------------------------------------------------- octree sampling

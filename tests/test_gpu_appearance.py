@@ -86,7 +86,8 @@ def test_render_sh_end_to_end_gradients():
     views = pr.make_views(cams, offs, cnts)
     x = H.to_dev(xyz)
     r = H.to_dev(raw).requires_grad_(True)
-    img, tf = pr.render_sh(x, r, views)
+    bw = torch.empty((sum(cnts),), dtype=torch.float32, device=H.DEV)
+    img, tf = pr.render_sh(x, r, views, blend_weight=bw)
     P = [c.width * c.height for c in cams]
     rng = np.random.default_rng(6)
     g_img = rng.normal(size=(sum(P), 4)).astype(np.float32)
@@ -116,6 +117,7 @@ def test_render_sh_end_to_end_gradients():
         e = np.abs(img[pix:pix + L.P] - ref["image"]) / np.maximum(mag, 1e-12)
         H.say(f"    view {v}: image err / sum T a |c| max {e.max():.3e}")
         assert e.max() <= H.REL_TOL
+        H.check_blend_weight(bw[sl].cpu().numpy(), L, o_gpu[sl], n)
         b = oracle.blend_backward(L, o_gpu[sl], f_gpu[sl], n, g_img[pix:pix + L.P])
         g_opa[sl] = b["grad_opa"]
         g_feat[sl] = b["grad_feat"]
