@@ -307,7 +307,7 @@ def bench_pipeline(pr, torch, np, workloads, log):
     def train_step():
         xs, lf, _ = pr.sample_view(tree, cam, n, seed=(1, 2))
         raw.grad = None
-        img, tf = pr.render_sh(xs, raw, views, blend_weight=bw)
+        img, tf = pr.render_sh(xs, raw, views, blend_weight=bw, blend_weight_in_backward=True)
         torch.autograd.backward([img], [g_img])
         pr.update_probabilities(tree, lf, bw)
     out["ms_train_step"] = round(time_ms(torch, train_step, reps=5), 4)

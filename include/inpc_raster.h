@@ -136,13 +136,17 @@ int inpc_rasterize_fwd(const float *xyz, const void *feat, int32_t feat_dtype,
  * settings must be those of the forward that filled ``saved``.
  * Writes grad_feat [N,F] f32 and grad_opacity [N] f32 in full (points that
  * produce no blended splat get exact zeros).  Deterministic: no float
- * atomics; every gradient is summed in a fixed order. */
+ * atomics; every gradient is summed in a fixed order.
+ * blend_weight [N] f32 (may be NULL): the same per-point blend weight as the
+ * forward's optional output, obtained here almost for free from the
+ * per-splat records the backward already reduces (training computes the
+ * probability updates after the backward). */
 int inpc_rasterize_bwd(const float *xyz, const void *feat, int32_t feat_dtype,
                        const float *opacity, int64_t n_points, int32_t F,
                        const inpc_camera_t *cam_host, const inpc_settings_t *settings_host,
                        const void *saved, size_t saved_bytes, const float *grad_image,
                        const float *grad_t_final, float *grad_feat, float *grad_opacity,
-                       void *ws, size_t ws_bytes, void *stream);
+                       float *blend_weight, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------- batched calls */
 
@@ -170,7 +174,8 @@ int inpc_rasterize_bwd_batched(const float *xyz, const void *feat, int32_t feat_
                                const inpc_settings_t *settings_host, const void *saved,
                                size_t saved_bytes, const float *grad_image,
                                const float *grad_t_final, float *grad_feat,
-                               float *grad_opacity, void *ws, size_t ws_bytes, void *stream);
+                               float *grad_opacity, float *blend_weight, void *ws,
+                               size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ appearance */
 

@@ -78,11 +78,11 @@ def lib():
         "inpc_plain_sizes": [i64, cam_p, i32, i32, i32, szp, szp, szp],
         "inpc_batched_sizes": [view_p, i32, i64, i32, i32, i32, szp, szp, szp],
         "inpc_rasterize_fwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, P, sz, P, sz, P],
-        "inpc_rasterize_bwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, sz, P, P, P, P, P, sz, P],
+        "inpc_rasterize_bwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, sz, P, P, P, P, P, P, sz, P],
         "inpc_rasterize_fwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, P, P, P, sz, P, sz,
                                        P],
         "inpc_rasterize_bwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, sz, P, P, P, P, P,
-                                       sz, P],
+                                       P, sz, P],
         "inpc_sum_view_grads": [view_p, i32, i64, i32, P, P, P, P, P, sz, P],
         "inpc_multisample_sizes": [i64, cam_p, P, P, i32, i32, i32, szp],
         "inpc_appearance_fwd": [P, P, i64, view_p, i32, P, P, i32, P, sz, P],
@@ -310,8 +310,10 @@ def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_
     return image, t_final, state
 
 
-def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None):
-    """Backward of a forward; returns float32 (grad_feat, grad_opa) per view point."""
+def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None, blend_weight=None):
+    """Backward of a forward; returns float32 (grad_feat, grad_opa) per view point.
+    ``blend_weight``: optional float32 tensor (one entry per view point) that
+    receives the per-point blend weights, computed from the backward's records."""
     g_img = g_img.contiguous().float()
     g_t = None if g_t is None else g_t.contiguous().float()
     nvp = sum(int(state.views[i].point_count) for i in range(state.n_views))
@@ -321,11 +323,12 @@ def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None):
     ws = _buffer(bws, dev)
     gf = torch.empty((nvp, state.F), dtype=torch.float32, device=dev)
     go = torch.empty((nvp,), dtype=torch.float32, device=dev)
+    _check_blend_weight(blend_weight, state.views, state.n_views, dev)
     _check(lib().inpc_rasterize_bwd_batched(_ptr(xyz), _ptr(feat), state.fdt, _ptr(opa), state.n_points,
                                             state.F, state.views, state.n_views,
                                             ctypes.byref(state.settings), _ptr(state.saved),
                                             state.saved.numel(), _ptr(g_img), _ptr(g_t), _ptr(gf),
-                                            _ptr(go), _ptr(ws), ws.numel(), _stream()),
+                                            _ptr(go), _ptr(blend_weight), _ptr(ws), ws.numel(), _stream()),
            "inpc_rasterize_bwd")
     return gf, go
 
@@ -480,10 +483,12 @@ class _ShRaster(torch.autograd.Function):
     bfloat16."""
 
     @staticmethod
-    def forward(ctx, xyz, raw, views, t_threshold, mode, tuning_id, feat_dtype, blend_weight):
+    def forward(ctx, xyz, raw, views, t_threshold, mode, tuning_id, feat_dtype, blend_weight, bw_in_backward):
         opa, feat = appearance_forward(xyz, raw, views, feat_dtype)
         image, t_final, state = _forward(xyz, feat, opa, views, len(views), t_threshold, mode, tuning_id,
-                                         False, None, blend_weight, ATTR_PER_VIEW_POINT)
+                                         False, None, None if bw_in_backward else blend_weight,
+                                         ATTR_PER_VIEW_POINT)
+        ctx.bw = blend_weight if bw_in_backward else None
         ctx.state = state
         ctx.views = views
         ctx.save_for_backward(xyz, raw, feat, opa)
@@ -494,26 +499,27 @@ class _ShRaster(torch.autograd.Function):
     def backward(ctx, g_img, g_t):
         xyz, raw, feat, opa = ctx.saved_tensors
         if g_img is None and g_t is None:
-            return (None,) * 8
+            return (None,) * 9
         st = ctx.state
         if g_img is None:
             P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
             g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
-        gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
-        return None, appearance_backward(xyz, raw, ctx.views, go, gf), None, None, None, None, None, None
+        gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t, ctx.bw)
+        return None, appearance_backward(xyz, raw, ctx.views, go, gf), None, None, None, None, None, None, None
 
 
 def render_sh(xyz, raw, views, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1,
-              feat_dtype=torch.float32, blend_weight=None):
+              feat_dtype=torch.float32, blend_weight=None, blend_weight_in_backward: bool = False):
     """Appearance step (opacity activation + degree-2 SH, per view point) then
     batched rasterization -> packed (image [sum P, 4], t_final [sum P]);
     differentiable with respect to ``raw`` [N, 37].  ``blend_weight``: optional
     float32 tensor (one entry per view point) that receives the per-point
-    blend weights of the forward."""
+    blend weights, written by the forward or (cheaper, for training) by the
+    backward when ``blend_weight_in_backward``."""
     if xyz.dtype != torch.float32 or not xyz.is_cuda:
         raise TypeError("xyz must be a float32 device tensor")
     return _ShRaster.apply(xyz.contiguous(), raw.contiguous(), views, t_threshold, mode, tuning_id, feat_dtype,
-                           blend_weight)
+                           blend_weight, bool(blend_weight_in_backward))
 
 
 # ---------------------------------------------------------------- octree sampling
@@ -726,7 +732,7 @@ class BatchedStep:
         _check(lib().inpc_rasterize_fwd_batched(
             _ptr(self.xyz), _ptr(self.feat), self.fdt, _ptr(self.opa), self.N, self.F, self.views,
             self.n_views, ctypes.byref(self.settings), _ptr(self.image), _ptr(self.t_final),
-            _ptr(self.blend_weight), _ptr(self.saved), self.saved.numel(), _ptr(self.fwd_ws),
+            None, _ptr(self.saved), self.saved.numel(), _ptr(self.fwd_ws),
             self.fwd_ws.numel(), _stream()),
             "inpc_rasterize_fwd_batched")
 
@@ -735,7 +741,8 @@ class BatchedStep:
             _ptr(self.xyz), _ptr(self.feat), self.fdt, _ptr(self.opa), self.N, self.F, self.views,
             self.n_views, ctypes.byref(self.settings), _ptr(self.saved), self.saved.numel(),
             _ptr(self.g_img), _ptr(self.g_t), _ptr(self.grad_feat), _ptr(self.grad_opa),
-            _ptr(self.bwd_ws), self.bwd_ws.numel(), _stream()), "inpc_rasterize_bwd_batched")
+            _ptr(self.blend_weight), _ptr(self.bwd_ws), self.bwd_ws.numel(), _stream()),
+            "inpc_rasterize_bwd_batched")
 
     def run(self):
         self.forward()

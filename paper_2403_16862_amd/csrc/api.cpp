@@ -21,14 +21,15 @@ namespace inpc {
 // zdigit / pdigit = 0: choose the digit width from the key width (fewest
 // passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
-    {0, 0, 16, 3, "depth and pixel sort auto digits, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {0, 0, 16, 4, "depth and pixel sort auto digits, 4096-key tiles, blend 16 lanes/pixel 2x2"},
-    {0, 0, 32, 3, "depth and pixel sort auto digits, 8192-key tiles, blend 8 lanes/pixel 4x2"},
-    {8, 8, 16, 3, "depth sort 8-bit, pixel sort 8-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {9, 11, 16, 3, "depth sort 9-bit, pixel sort 11-bit, 4096-key tiles, blend 8 lanes/pixel 4x2"},
-    {0, 0, 16, 2, "depth and pixel sort auto digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {0, 0, 16, 1, "depth and pixel sort auto digits, 4096-key tiles, blend 2 lanes/pixel 8x4"},
-    {0, 0, 16, 0, "depth and pixel sort auto digits, 4096-key tiles, blend 1 lane/pixel 8x8"},
+    {0, 0, 16, 3, 4, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
+    {0, 0, 16, 3, 3, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 8 lanes/pixel 4x2"},
+    {0, 0, 16, 4, 4, "auto digits, 4096-key tiles, blend fwd 16 lanes/pixel 2x2, bwd 16 lanes/pixel 2x2"},
+    {0, 0, 32, 3, 4, "auto digits, 8192-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
+    {8, 8, 16, 3, 4, "depth sort 8-bit, pixel sort 8-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
+    {9, 11, 16, 3, 4, "depth sort 9-bit, pixel sort 11-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
+    {0, 0, 16, 2, 2, "auto digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {0, 0, 16, 1, 1, "auto digits, 4096-key tiles, blend 2 lanes/pixel 8x4"},
+    {0, 0, 16, 0, 0, "auto digits, 4096-key tiles, blend 1 lane/pixel 8x8"},
 };
 
 int auto_digit(int bits) {
@@ -42,6 +43,12 @@ static int zdigit_of(const Tuning& t, int bits) { return t.zdigit ? t.zdigit : a
 static int pdigit_of(const Tuning& t, int bits) { return t.pdigit ? t.pdigit : auto_digit(bits); }
 constexpr int kNumTunings = (int)(sizeof(kTunings) / sizeof(kTunings[0]));
 constexpr int kDefaultTuning = 0;
+
+// The backward may use its own blend shape, except in RECOMPUTE mode: there it
+// rebuilds T_k with the forward's group recurrence, whose grouping must match.
+static int bwd_shape_of(int tid, int mode) {
+    return mode == INPC_RECOMPUTE ? kTunings[tid].blend_shape : kTunings[tid].bwd_shape;
+}
 
 int tuning_count() { return kNumTunings; }
 const Tuning& tuning(int id) { return kTunings[id]; }
@@ -418,7 +425,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
 static int backward(const Problem& pb, int tid, float tau, const float* xyz, const void* feat,
                     const float* opacity, const void* saved, size_t saved_bytes,
                     const float* g_img, const float* g_t, float* grad_feat, float* grad_opa,
-                    void* ws, size_t ws_bytes, hipStream_t s) {
+                    float* blend_weight, void* ws, size_t ws_bytes, hipStream_t s) {
     const Layout L = make_layout(pb);
     if (saved_bytes < L.saved_bytes || ws_bytes < L.bwd_bytes) return INPC_EWORKSPACE;
     if (pb.n_vp > 0 && (!saved || !ws)) return INPC_EINVAL;
@@ -447,7 +454,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     }
     {
     ProfScope p(kStBlendBwd, s);
-    launch_blend_bwd(pb.F, pb.fdt, tn.blend_shape, views, (int)pb.views.size(), pb.n_tiles,
+    launch_blend_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
                      at<const uint2>(const_cast<void*>(frag_base), fo->range),
                      at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
                      at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
@@ -458,7 +465,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     ProfScope p(kStPointReduce, s);
     launch_point_reduce(pb.F, views, (int)pb.views.size(), pb.n_vp,
                         at<const PointRec>(const_cast<void*>(frag_base), fo->rec), frec, g_img,
-                        grad_feat, grad_opa, s);
+                        grad_feat, grad_opa, blend_weight, s);
     return check_launch("inpc backward");
 }
 
@@ -622,7 +629,8 @@ static int ms_impl(const float* xyz, const void* feat, int fdt, const float* opa
 static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
                     int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
                     const void* saved, size_t saved_bytes, const float* g_img, const float* g_t,
-                    float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes, void* stream) {
+                    float* grad_feat, float* grad_opa, float* blend_weight, void* ws, size_t ws_bytes,
+                    void* stream) {
     int treq, mode;
     float tau;
     bool avp;
@@ -632,18 +640,19 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb, avp);
     if (rc) return rc;
     const int tid = resolve_tuning(treq, pb);
-    if (shape_of(tid) != 0) {
-        rc = make_problem(views, n_views, n_points, F, fdt, mode, shape_of(tid), pb, avp);
+    if (bwd_shape_of(tid, mode) != 0) {
+        rc = make_problem(views, n_views, n_points, F, fdt, mode, bwd_shape_of(tid, mode), pb, avp);
         if (rc) return rc;
     }
     rc = check_arrays(pb, xyz, feat, opa);
     if (rc) return rc;
+    if (blend_weight && !aligned(blend_weight, 4)) return INPC_EINVAL;
     if (!g_img || !aligned(g_img, 16) || (g_t && !aligned(g_t, 4))) return INPC_EINVAL;
     if (pb.n_vp > 0 && (!grad_feat || !grad_opa || !aligned(grad_feat, 16) || !aligned(grad_opa, 4)))
         return INPC_EINVAL;
     if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
-    return backward(pb, tid, tau, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa, ws,
-                    ws_bytes, static_cast<hipStream_t>(stream));
+    return backward(pb, tid, tau, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa,
+                    blend_weight, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // namespace inpc
@@ -694,11 +703,11 @@ int inpc_rasterize_bwd(const float* xyz, const void* feat, int32_t fdt, const fl
                        int64_t n_points, int32_t F, const inpc_camera_t* cam,
                        const inpc_settings_t* st, const void* saved, size_t saved_bytes,
                        const float* g_img, const float* g_t, float* grad_feat, float* grad_opa,
-                       void* ws, size_t ws_bytes, void* stream) {
+                       float* blend_weight, void* ws, size_t ws_bytes, void* stream) {
     if (!cam) return INPC_EINVAL;
     const inpc_view_t v = single_view(cam, n_points);
     return bwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, saved, saved_bytes, g_img, g_t,
-                    grad_feat, grad_opa, ws, ws_bytes, stream);
+                    grad_feat, grad_opa, blend_weight, ws, ws_bytes, stream);
 }
 
 int inpc_rasterize_fwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,
@@ -714,10 +723,10 @@ int inpc_rasterize_bwd_batched(const float* xyz, const void* feat, int32_t fdt, 
                                int64_t n_points, int32_t F, const inpc_view_t* views,
                                int32_t n_views, const inpc_settings_t* st, const void* saved,
                                size_t saved_bytes, const float* g_img, const float* g_t,
-                               float* grad_feat, float* grad_opa, void* ws, size_t ws_bytes,
-                               void* stream) {
+                               float* grad_feat, float* grad_opa, float* blend_weight, void* ws,
+                               size_t ws_bytes, void* stream) {
     return bwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, st, saved, saved_bytes, g_img,
-                    g_t, grad_feat, grad_opa, ws, ws_bytes, stream);
+                    g_t, grad_feat, grad_opa, blend_weight, ws, ws_bytes, stream);
 }
 
 int inpc_sum_view_grads(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F,
@@ -1083,7 +1092,7 @@ int inpc_autotune(const float* xyz, const void* feat, int32_t fdt, const float* 
                              saved, saved_bytes, ws, ws_bytes, stream);
             if (r || !g_img) return r;
             return bwd_impl(xyz, feat, fdt, opa, n_points, F, views, n_views, &st, saved, saved_bytes,
-                            g_img, nullptr, grad_feat, grad_opa, ws, ws_bytes, stream);
+                            g_img, nullptr, grad_feat, grad_opa, nullptr, ws, ws_bytes, stream);
         };
         rc = step();
         if (rc) break;

@@ -15,7 +15,8 @@ struct Tuning {
     int zdigit;       // digit bits of the per-point depth sort (0: from the key width)
     int pdigit;       // digit bits of the per-fragment pixel sort (0: from the key width)
     int sort_items;   // keys per thread in a sort tile (tile = 256 * items)
-    int blend_shape;  // blend: lanes per pixel and wave tile, see blend_shape_dims()
+    int blend_shape;  // forward blend: lanes per pixel and wave tile, see blend_shape_dims()
+    int bwd_shape;    // backward blend shape
     const char* name;
 };
 
@@ -133,7 +134,7 @@ void launch_blend_bwd(int F, int feat_dtype, int shape, const GpuView* views, in
 
 void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
                          const PointRec* rec, const float2* frec, const float* g_img,
-                         float* grad_feat, float* grad_opa, hipStream_t s);
+                         float* grad_feat, float* grad_opa, float* blend_weight, hipStream_t s);
 
 void launch_sum_view_grads(const GpuView* views, int n_views, int64_t n_points, int F,
                            const float* vg_feat, const float* vg_opa, float* g_feat, float* g_opa,

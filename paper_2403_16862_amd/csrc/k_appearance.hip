@@ -4,16 +4,38 @@
 // plus its backward.  Raw rows are [1 + 36] floats: the opacity logit, then
 // coefficient (basis j, channel c) at 1 + 4 j + c.
 //
-// Rows of 37 floats are not 16-byte aligned, so a block stages the rows of
-// its 256 points through LDS with coalesced dword accesses (one wave touches
-// 256 contiguous bytes per instruction) and each thread then reads its own
-// row at an odd LDS stride (37 words: no bank conflicts).
+// Rows of 37 floats are not 16-byte aligned individually, but the rows of a
+// block of 256 points are one contiguous run: a block stages them through
+// LDS with coalesced 16-byte accesses (dwords where the run is not aligned)
+// and each thread then reads its own row at an odd LDS stride (37 words: no
+// bank conflicts).
 #include "internal.h"
 
 namespace inpc {
 
 constexpr int kRawW = 37;
 constexpr int kApBlock = 256;
+
+// Block copy of ``n`` floats between global memory and LDS: 16-byte accesses
+// when both sides allow them, dwords for the rest.
+template <bool TO_LDS>
+__device__ __forceinline__ void stage_rows(float* __restrict__ lds, float* __restrict__ glob, int n) {
+    int done = 0;
+    if ((reinterpret_cast<uintptr_t>(glob) & 15u) == 0) {
+        const int n4 = n >> 2;
+        float4* l4 = reinterpret_cast<float4*>(lds);
+        float4* g4 = reinterpret_cast<float4*>(glob);
+        for (int e = threadIdx.x; e < n4; e += kApBlock) {
+            if constexpr (TO_LDS) l4[e] = g4[e];
+            else g4[e] = l4[e];
+        }
+        done = n4 << 2;
+    }
+    for (int e = done + threadIdx.x; e < n; e += kApBlock) {
+        if constexpr (TO_LDS) lds[e] = glob[e];
+        else glob[e] = lds[e];
+    }
+}
 
 // Real SH basis of degree <= 2 at the unit direction (x, y, z), in the order
 // (0,0), (1,-1), (1,0), (1,1), (2,-2), (2,-1), (2,0), (2,1), (2,2); the real
@@ -58,7 +80,7 @@ __global__ __launch_bounds__(kApBlock) void k_appearance_fwd(const float* __rest
                                                              const GpuView* __restrict__ views, int n_views,
                                                              int64_t n_vp, float* __restrict__ opa_out,
                                                              void* __restrict__ feat_out) {
-    __shared__ float s_raw[kApBlock * kRawW];
+    __shared__ __align__(16) float s_raw[kApBlock * kRawW];
     const int64_t vp0 = (int64_t)blockIdx.x * kApBlock;
     const int rows = (int)((n_vp - vp0) < kApBlock ? (n_vp - vp0) : kApBlock);
     auto vstart = [](const GpuView& g) { return g.vpoint_offset; };
@@ -67,10 +89,9 @@ __global__ __launch_bounds__(kApBlock) void k_appearance_fwd(const float* __rest
     // Fast path: all rows of the block belong to one view, so their raw rows
     // are contiguous in memory.
     const bool one_view = vp0 + rows <= V0.vpoint_offset + V0.point_count;
-    if (one_view) {
-        const float* src = raw + (V0.point_offset + (vp0 - V0.vpoint_offset)) * kRawW;
-        for (int e = threadIdx.x; e < rows * kRawW; e += kApBlock) s_raw[e] = src[e];
-    }
+    if (one_view)
+        stage_rows<true>(s_raw, const_cast<float*>(raw) + (V0.point_offset + (vp0 - V0.vpoint_offset)) * kRawW,
+                         rows * kRawW);
     __syncthreads();
     const int64_t vp = vp0 + threadIdx.x;
     if (vp >= n_vp) return;
@@ -118,7 +139,7 @@ __global__ __launch_bounds__(kApBlock) void k_appearance_bwd(const float* __rest
                                                              int64_t n_points, const float* __restrict__ g_opa,
                                                              const float* __restrict__ g_feat,
                                                              float* __restrict__ grad_raw) {
-    __shared__ float s_out[kApBlock * kRawW];
+    __shared__ __align__(16) float s_out[kApBlock * kRawW];
     const int64_t p0 = (int64_t)blockIdx.x * kApBlock;
     const int rows = (int)((n_points - p0) < kApBlock ? (n_points - p0) : kApBlock);
     const int64_t p = p0 + threadIdx.x;
@@ -149,8 +170,7 @@ __global__ __launch_bounds__(kApBlock) void k_appearance_bwd(const float* __rest
         for (int j = 0; j < kRawW; ++j) s_out[threadIdx.x * kRawW + j] = (float)acc[j];
     }
     __syncthreads();
-    float* dst = grad_raw + p0 * kRawW;
-    for (int e = threadIdx.x; e < rows * kRawW; e += kApBlock) dst[e] = s_out[e];
+    stage_rows<false>(s_out, grad_raw + p0 * kRawW, rows * kRawW);
 }
 
 void launch_appearance_fwd(const float* xyz, const float* raw, const GpuView* views, int n_views,

@@ -7,6 +7,7 @@ namespace inpc {
 
 // --------------------------------------------------- per-point reduction
 // grad_opa[vp] = sum_c w_c dL/dalpha_c, grad_feat[vp] = sum_c T_c alpha_c g_{pixel(c)}
+// and, if requested, the blend weight b[vp] = sum_c w_c T_c alpha_c
 // over the existing corners c = 0..3 in ascending order; the per-splat
 // records of a point are contiguous (ids 4vp .. 4vp+3), so this is a
 // segmented reduction over the id-ordered splat records.  Non-blended
@@ -15,7 +16,7 @@ template <int FM, bool DYN>
 __global__ __launch_bounds__(256) void k_point_reduce(
     const GpuView* __restrict__ views, int n_views, int64_t n_vp, const PointRec* __restrict__ rec,
     const float2* __restrict__ frec, const float* __restrict__ g_img, int Fd,
-    float* __restrict__ grad_feat, float* __restrict__ grad_opa) {
+    float* __restrict__ grad_feat, float* __restrict__ grad_opa, float* __restrict__ blend_weight) {
     const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (vp >= n_vp) return;
     const PointRec pr = rec[vp];
@@ -24,7 +25,7 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     double gf[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) gf[f] = 0.0;
-    double go = 0.0;
+    double go = 0.0, bw = 0.0;
     if (mask != 0u) {
         const int v = n_views == 1 ? 0
                                    : find_view(views, n_views, vp,
@@ -41,6 +42,7 @@ __global__ __launch_bounds__(256) void k_point_reduce(
             float wx, wy;
             corner_factors(pr.ax, pr.ay, c, wx, wy);
             go = __builtin_fma((double)wx * (double)wy, (double)da[c], go);
+            bw = __builtin_fma((double)wx * (double)wy, (double)ta[c], bw);
             const int64_t q = V.pixel_offset + (int64_t)(y0 + (c >> 1)) * V.W + (x0 + (c & 1));
             float g[FM];
             f32_row<FM, DYN>(g_img, q, Fd, g);
@@ -53,6 +55,7 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     for (int f = 0; f < FM; ++f) out[f] = (float)gf[f];
     f32_store<FM, DYN>(grad_feat, vp, Fd, out);
     grad_opa[vp] = (float)go;
+    if (blend_weight) blend_weight[vp] = (float)bw;
 }
 
 // ------------------------------------------------ per-point blend weight
@@ -164,12 +167,12 @@ __global__ __launch_bounds__(256) void k_sum_view_grads(
 
 void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
                          const PointRec* rec, const float2* frec, const float* g_img,
-                         float* grad_feat, float* grad_opa, hipStream_t s) {
+                         float* grad_feat, float* grad_opa, float* blend_weight, hipStream_t s) {
     if (n_vp == 0) return;
     const unsigned blocks = (unsigned)((n_vp + 255) / 256);
     dispatch_f(F, [&]<int FM, bool DYN>() {
         hipLaunchKernelGGL((k_point_reduce<FM, DYN>), dim3(blocks), dim3(256), 0, s, views, n_views, n_vp,
-                           rec, frec, g_img, F, grad_feat, grad_opa);
+                           rec, frec, g_img, F, grad_feat, grad_opa, blend_weight);
     });
 }
 

@@ -121,3 +121,19 @@ def test_blend_weight_in_graph_replay():
         L = oracle.fragments(b.xyz[sl], b.cams[v])
         H.check_blend_weight(bw[vp_off[v]:vp_off[v + 1]], L, b.opa[sl],
                              nb[pix_off[v]:pix_off[v + 1]].astype(np.int32))
+
+
+@pytest.mark.parametrize("mode", ["save", "recompute"])
+def test_blend_weight_from_backward(mode):
+    """The backward's per-point reduction yields the same weights (from its own
+    T_k alpha_k records) as the forward's optional output."""
+    s = workloads.config2(n=300_000)
+    lists = oracle.fragments(s.xyz, s.cam)
+    x, f, o = H.to_dev(s.xyz), H.to_dev(s.feat), H.to_dev(s.opa)
+    img, tf, st = pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save", keep_workspace=True)
+    n_gpu = H.check_fragments(dict(state=st), lists)
+    img2, tf2, st2 = pr.rasterize_forward(x, f, o, s.cam, 1e-4, mode)
+    bw = torch.full((s.n,), float("nan"), dtype=torch.float32, device=H.DEV)
+    gf, go = pr.rasterize_backward(x, f, o, st2, H.to_dev(s.g_img), None, bw)
+    torch.cuda.synchronize()
+    H.check_blend_weight(bw.cpu().numpy(), lists, s.opa, n_gpu)
