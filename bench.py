@@ -44,18 +44,22 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses):
+def stage_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses, E=None, n_tiles=None):
     """Compulsory bytes per step of each stage (each input read once, each
-    output written once; see the design notes for the derivation)."""
+    output written once).  Per-pixel lists store and sort the M splats; tile
+    lists store and sort E tile entries with one range per tile."""
+    items = M if E is None else E        # list items emitted, sorted and read by the blends
+    blended = M_b if E is None else E    # list items a blend reads
+    R = P if E is None else n_tiles      # ranges
     return {
         "project": 12 * N + 4 * N + 16 * N + 8 * N,
-        "sort_upsweep": zpasses * 4 * N + ppasses * 4 * M,
-        "sort_downsweep": zpasses * 16 * N + ppasses * 16 * M,
-        "emit": 4 * N + 4 * N + 16 * N_vis + 8 * M,
-        "ranges": 8 * P + 4 * M,
-        "blend_fwd": 8 * P + 4 * M_b + (16 + F * feat_bytes) * N_vis + (4 * F + 4 + 16) * P + 4 * M_b,
+        "sort_upsweep": zpasses * 4 * N + ppasses * 4 * items,
+        "sort_downsweep": zpasses * 16 * N + ppasses * 16 * items,
+        "emit": 4 * N + 4 * N + 16 * N_vis + 8 * items,
+        "ranges": 8 * R + 4 * items,
+        "blend_fwd": 8 * R + 4 * blended + (16 + F * feat_bytes) * N_vis + (4 * F + 4 + 16) * P + 4 * M_b,
         "clear_records": 32 * N,
-        "blend_bwd": 8 * P + 16 * P + 4 * M_b + 4 * M_b + (16 + F * feat_bytes) * N_vis + 4 * F * P + 8 * M_b,
+        "blend_bwd": 8 * R + 16 * P + 4 * blended + 4 * M_b + (16 + F * feat_bytes) * N_vis + 4 * F * P + 8 * M_b,
         "point_reduce": 16 * N + 32 * N + 4 * F * min(P, 4 * N_vis) + (4 * F + 4) * N,
     }
 
@@ -148,6 +152,7 @@ def main():
     M = int(keys.shape[0])
     M_b = int(nb.astype(np.int64).sum())
     N_vis = int(np.unique(ids >> 2).size)
+    items, layout = pr.state_info(st)
     del keys, ids, st
     P = s.cam.width * s.cam.height
     value = M / (ms_per_step * 1e-3)
@@ -159,8 +164,14 @@ def main():
     zbits = max(1, zspan.bit_length())
     pbits = max(1, (P - 1).bit_length())
     zpasses = sort_passes(tn[tid], "depth", zbits)
-    ppasses = sort_passes(tn[tid], "pixel", pbits)
-    model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses)
+    if layout:
+        ts = 16 if layout == 5 else 8
+        n_tiles = ((s.cam.width + ts - 1) // ts) * ((s.cam.height + ts - 1) // ts)
+        ppasses = sort_passes(tn[tid], "pixel", max(1, (n_tiles - 1).bit_length()))
+        model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses, E=items, n_tiles=n_tiles)
+    else:
+        ppasses = sort_passes(tn[tid], "pixel", pbits)
+        model = stage_bytes(s.n, N_vis, M, M_b, P, s.F, 4, zpasses, ppasses)
     per_step = {k: (v[0] / args.steps, v[1] / args.steps) for k, v in stages.items() if v[1] > 0}
     leaf = {k: v for k, v in per_step.items() if k in model}
     dom = max(leaf, key=lambda k: leaf[k][0])
@@ -193,6 +204,8 @@ def main():
                                "forward+backward through torch.autograd.Function",
                    "points": s.n, "width": s.cam.width, "height": s.cam.height, "features": s.F,
                    "fragments": M, "blended_fragments": M_b, "visible_points": N_vis,
+                   "list_layout": "tile entries %dx%d" % ((16, 16) if layout == 5 else (8, 8)) if layout
+                   else "per-pixel splat lists", "list_items": items,
                    "t_threshold": 1e-4, "tuning": tn[tid]},
         "model_gbs": round(total_model / (ms_per_step * 1e-3) / 1e9, 1),
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items()},

@@ -287,6 +287,14 @@ int inpc_sum_view_grads(const inpc_view_t *views_host, int32_t n_views, int64_t 
                         float *grad_feat, float *grad_opacity, void *ws, size_t ws_bytes,
                         void *stream);
 
+/* What a forward stored (synchronises the stream): *stored_items = number of
+ * list items (splats for per-pixel lists, tile entries for tile lists) and
+ * *layout = 0 for per-pixel lists or the tile-list blend shape (5: 16x16,
+ * 6: 8x8 tiles).  Arguments as for inpc_debug_fragments. */
+int inpc_state_info(const inpc_view_t *views_host, int32_t n_views, int64_t n_points, int32_t F,
+                    int32_t feat_dtype, const void *saved, size_t saved_bytes,
+                    int64_t *stored_items, int32_t *layout, void *stream);
+
 /* ----------------------------------------------------------- autotuning */
 
 /* Number of entries of the tuning table and a printable description. */

@@ -102,6 +102,8 @@ def lib():
         "inpc_tuning_for": [view_p, i32, i64, i32, i32],
         "inpc_debug_fragments": [view_p, i32, i64, i32, i32, P, sz, P, sz, P, P, i64,
                                  ctypes.POINTER(ctypes.c_int64), P, P],
+        "inpc_state_info": [view_p, i32, i64, i32, i32, P, sz, ctypes.POINTER(ctypes.c_int64),
+                            ctypes.POINTER(ctypes.c_int32), P],
         "inpc_profile_stage_count": [],
         "inpc_profile_stage_name": [i32],
         "inpc_profile_begin": [],
@@ -661,6 +663,16 @@ def debug_fragments(state: ForwardState):
                                   ids.ctypes.data_as(ctypes.c_void_p), m.value, ctypes.byref(m), None,
                                   _stream()), "inpc_debug_fragments")
     return keys, ids, nb
+
+
+def state_info(state: ForwardState):
+    """(stored list items, layout): splats and 0 for per-pixel lists, tile
+    entries and the tile blend shape (5: 16x16, 6: 8x8) for tile lists."""
+    items, layout = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().inpc_state_info(state.views, state.n_views, state.n_points, state.F, state.fdt, _ptr(state.saved),
+                                 state.saved.numel(), ctypes.byref(items), ctypes.byref(layout), _stream()),
+           "inpc_state_info")
+    return int(items.value), int(layout.value)
 
 
 # --------------------------------------------------------------- stage timing

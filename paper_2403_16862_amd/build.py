@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinpc_raster.so")
 SOURCES = ["k_project.hip", "k_sort.hip", "k_blend_fwd.hip", "k_blend_bwd.hip", "k_reduce.hip",
-           "k_appearance.hip", "k_sampling.hip", "api.cpp"]
+           "k_appearance.hip", "k_sampling.hip", "k_tile.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

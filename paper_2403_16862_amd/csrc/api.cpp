@@ -21,6 +21,9 @@ namespace inpc {
 // zdigit / pdigit = 0: choose the digit width from the key width (fewest
 // passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
+    {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
+    {0, 0, 32, kTileShape8, kTileShape8, "auto digits, 8192-key tiles, tile-list blend 8x8 (entries per tile)"},
+    {0, 0, 16, kTileShape16, kTileShape16, "auto digits, 4096-key tiles, tile-list blend 16x16 (entries per tile)"},
     {0, 0, 16, 3, 4, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
     {0, 0, 16, 3, 3, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 8 lanes/pixel 4x2"},
     {0, 0, 16, 4, 4, "auto digits, 4096-key tiles, blend fwd 16 lanes/pixel 2x2, bwd 16 lanes/pixel 2x2"},
@@ -79,6 +82,8 @@ struct Problem {
     uint32_t zbase = 0;      // depth key = float bits of z - zbase
     uint32_t zkey_none = 0;  // depth key of points without splats (> every real key)
     int zbits = 32;          // key bits of the depth sort
+    int tile_bits = 1;       // key bits of the tile sort at the blend shape's tile grid
+    int tile_bits_max = 1;   // the same for the smallest tiles (sizes the sort scratch)
 };
 
 static bool finite_f(float x) { return std::isfinite(x); }
@@ -143,6 +148,15 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
     pb.n_vp = vp;
     pb.n_pixels = pix;
     pb.n_tiles = tiles;
+    int64_t tiles8 = 0;
+    for (const GpuView& g : pb.views) tiles8 += (int64_t)((g.W + 7) / 8) * ((g.H + 7) / 8);
+    auto bits_for = [](int64_t n) {
+        int b = 1;
+        while (b < 32 && (((int64_t)1 << b) < n)) ++b;
+        return b;
+    };
+    pb.tile_bits = bits_for(tiles);
+    pb.tile_bits_max = bits_for(tiles8);
     int bits = 0;
     while (bits < 32 && (((int64_t)1 << bits) < pix)) ++bits;
     pb.pixel_bits = bits;
@@ -199,6 +213,8 @@ static size_t max_counts_words(const Problem& pb) {
         const Tuning& t = kTunings[i];
         w = std::max(w, sort_counts_words(zdigit_of(t, pb.zbits), t.sort_items, pb.n_vp));
         w = std::max(w, sort_counts_words(pdigit_of(t, pb.pixel_bits), t.sort_items, 4 * pb.n_vp));
+        w = std::max(w, sort_counts_words(pdigit_of(t, pb.tile_bits_max), t.sort_items, 4 * pb.n_vp));
+        w = std::max(w, sort_counts_words(pdigit_of(t, pb.tile_bits_max - 1), t.sort_items, 4 * pb.n_vp));
     }
     return w;
 }
@@ -345,9 +361,11 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     PointRec* rec = at<PointRec>(frag_base, fo.rec);
     uint32_t* zk_in = at<uint32_t>(build_base, bo.zk_in);
     uint32_t* zv_in = at<uint32_t>(build_base, bo.zv_in);
+    const bool tile = is_tile_shape(tn.blend_shape);
     {
         ProfScope p(kStProject, s);
-        launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in, s);
+        launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in,
+                       tile ? tile_log2_of(tn.blend_shape) : 0, s);
     }
     uint32_t* zk_a = at<uint32_t>(build_base, bo.zk_a);
     uint32_t* zv_a = at<uint32_t>(build_base, bo.zv_a);
@@ -362,10 +380,11 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     const int zp = radix_passes(zdigit_of(tn, pb.zbits), pb.zbits);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
 
-    // Pixel sort: emission writes (kb, vb); the sorted ids must end in the
-    // fragment-state id buffer.
-    const int pdig = pdigit_of(tn, pb.pixel_bits);
-    const int pp = radix_passes(pdig, pb.pixel_bits);
+    // Pixel sort (or tile sort of tile entries): emission writes (kb, vb);
+    // the sorted values must end in the fragment-state id buffer.
+    const int kbits = tile ? pb.tile_bits : pb.pixel_bits;
+    const int pdig = pdigit_of(tn, kbits);
+    const int pp = radix_passes(pdig, kbits);
     uint32_t* ids_final = at<uint32_t>(frag_base, fo.ids);
     uint32_t* pv_other = at<uint32_t>(build_base, bo.pv_other);
     uint32_t* pk_a = at<uint32_t>(build_base, bo.pk_a);
@@ -374,18 +393,23 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* pv_b = (pp & 1) ? pv_other : ids_final;
     {
         ProfScope p(kStEmit, s);
-        launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
-                    pv_b, s);
+        if (tile)
+            launch_tile_emit(zv_sorted, rec, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
+                             at<uint32_t>(build_base, bo.chunks), m_dev, pk_b, pv_b, s);
+        else
+            launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
+                        pv_b, s);
     }
     {
         ProfScope p(kStPixelSort, s);
-        launch_radix_sort(pdig, tn.sort_items, pb.pixel_bits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
+        launch_radix_sort(pdig, tn.sort_items, kbits, pk_b, pv_b, pk_a, pv_a, pk_b, pv_b,
                           m_dev, 4 * pb.n_vp, counts, s);
     }
     const uint32_t* pk_sorted = (pp & 1) ? pk_a : pk_b;
     {
         ProfScope p(kStRanges, s);
-        launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, pb.n_pixels, at<uint2>(frag_base, fo.range), s);
+        launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, tile ? pb.n_tiles : pb.n_pixels,
+                      at<uint2>(frag_base, fo.range), s);
     }
 }
 
@@ -406,13 +430,22 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     float* splat_weight = blend_weight ? at<float>(ws, L.fwd_build.pv_other) : nullptr;
     if (splat_weight)
         launch_fill_u32(reinterpret_cast<uint32_t*>(splat_weight), 0u, (size_t)4 * pb.n_vp, s);
+    // word 1 of the scalars records which fragment layout the state holds
+    launch_fill_u32(m_dev + 1, is_tile_shape(tn.blend_shape) ? (uint32_t)tn.blend_shape : 0u, 1, s);
     {
         ProfScope p(kStBlendFwd, s);
-        launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
-                         (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
-                         at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
-                         image, t_final, at<PixelState>(saved, L.s_state),
-                         pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr, splat_weight, s);
+        float* tk = pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr;
+        if (is_tile_shape(tn.blend_shape))
+            launch_tile_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
+                            (int)pb.views.size(), pb.n_tiles,
+                            at<uint2>(frag_base, fo.range), at<uint32_t>(frag_base, fo.ids),
+                            at<PointRec>(frag_base, fo.rec), feat, tau, image, t_final,
+                            at<PixelState>(saved, L.s_state), tk, splat_weight, s);
+        else
+            launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
+                             (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
+                             at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
+                             image, t_final, at<PixelState>(saved, L.s_state), tk, splat_weight, s);
     }
     if (blend_weight) {
         ProfScope p(kStBlendWeight, s);
@@ -454,13 +487,22 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     }
     {
     ProfScope p(kStBlendBwd, s);
-    launch_blend_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
-                     at<const uint2>(const_cast<void*>(frag_base), fo->range),
-                     at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
-                     at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
-                     at<const PixelState>(sv, L.s_state), g_img, g_t,
-                     at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
-                     frec, s);
+    if (is_tile_shape(bwd_shape_of(tid, pb.mode)))
+        launch_tile_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
+                        at<const uint2>(const_cast<void*>(frag_base), fo->range),
+                        at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
+                        at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
+                        at<const PixelState>(sv, L.s_state), g_img, g_t,
+                        at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
+                        frec, s);
+    else
+        launch_blend_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
+                         at<const uint2>(const_cast<void*>(frag_base), fo->range),
+                         at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
+                         at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
+                         at<const PixelState>(sv, L.s_state), g_img, g_t,
+                         at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
+                         frec, s);
     }
     ProfScope p(kStPointReduce, s);
     launch_point_reduce(pb.F, views, (int)pb.views.size(), pb.n_vp,
@@ -953,6 +995,25 @@ int inpc_update_probabilities(const int32_t* leaf_index, const float* blend_weig
     return check_launch("inpc_update_probabilities");
 }
 
+int inpc_state_info(const inpc_view_t* views, int32_t n_views, int64_t n_points, int32_t F, int32_t fdt,
+                    const void* saved, size_t saved_bytes, int64_t* stored_items, int32_t* layout,
+                    void* stream) {
+    Problem pb;
+    int rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, 0, pb);
+    if (rc) return rc;
+    if (!saved || !stored_items || !layout) return INPC_EINVAL;
+    const Layout L = make_layout(pb);
+    if (saved_bytes < L.saved_bytes) return INPC_EWORKSPACE;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "inpc_state_info sync");
+    uint32_t sc[2] = {0, 0};
+    e = hipMemcpy(sc, at<const uint32_t>(const_cast<void*>(saved), L.s_scalars), 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "inpc_state_info copy");
+    *stored_items = sc[0];
+    *layout = (int32_t)sc[1];
+    return INPC_OK;
+}
+
 int inpc_tuning_count(void) { return kNumTunings; }
 
 const char* inpc_tuning_name(int32_t id) {
@@ -983,10 +1044,11 @@ int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_po
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments sync");
-    uint32_t m = 0;
-    e = hipMemcpy(&m, at<const uint32_t>(const_cast<void*>(saved), L.s_scalars), 4, hipMemcpyDeviceToHost);
+    uint32_t sc[2] = {0, 0};
+    e = hipMemcpy(sc, at<const uint32_t>(const_cast<void*>(saved), L.s_scalars), 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
-    *m_out = m;
+    const uint32_t m = sc[0];
+    const bool tile = is_tile_shape((int)sc[1]);
     if (n_blended_host) {
         std::vector<PixelState> st((size_t)pb.n_pixels);
         e = hipMemcpy(st.data(), at<const PixelState>(const_cast<void*>(saved), L.s_state),
@@ -994,31 +1056,87 @@ int inpc_debug_fragments(const inpc_view_t* views, int32_t n_views, int64_t n_po
         if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
         for (size_t q = 0; q < st.size(); ++q) n_blended_host[q] = st[q].n_blended;
     }
-    if (!keys_host || !ids_host || cap < (int64_t)m) return INPC_OK;
-    std::vector<uint2> range((size_t)pb.n_pixels);
-    std::vector<uint32_t> zk((size_t)pb.n_vp);
-    if (m) {
-        e = hipMemcpy(ids_host, at<const uint32_t>(const_cast<void*>(saved), L.saved_frag.ids),
-                      (size_t)m * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
-    }
-    e = hipMemcpy(range.data(), at<const uint2>(const_cast<void*>(saved), L.saved_frag.range),
-                  range.size() * sizeof(uint2), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
-    if (!zk.empty()) {
-        e = hipMemcpy(zk.data(), at<const uint32_t>(const_cast<void*>(fwd_ws), L.fwd_build.zk_in),
-                      zk.size() * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "inpc_debug_fragments copy");
-    }
-    // Keys from the device's own data: the pixel that owns each sorted slot
-    // (from the per-pixel ranges) and the depth bits of the slot's point.
-    for (int64_t q = 0; q < pb.n_pixels; ++q) {
-        for (uint32_t i = range[q].x; i < range[q].y && i < m; ++i) {
-            const uint32_t vp = ids_host[i] >> 2;
-            const uint32_t zb = vp < zk.size() ? zk[vp] + pb.zbase : 0xFFFFFFFFu;
-            keys_host[i] = ((uint64_t)q << 32) | zb;
+    auto copy = [&](void* dst, const void* src, size_t bytes) -> int {
+        if (!bytes) return INPC_OK;
+        const hipError_t err = hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost);
+        return err == hipSuccess ? INPC_OK : hip_fail(err, "inpc_debug_fragments copy");
+    };
+    if (!tile) {
+        *m_out = m;
+        if (!keys_host || !ids_host || cap < (int64_t)m) return INPC_OK;
+        std::vector<uint2> range((size_t)pb.n_pixels);
+        std::vector<uint32_t> zk((size_t)pb.n_vp);
+        if ((rc = copy(ids_host, at<const uint32_t>(const_cast<void*>(saved), L.saved_frag.ids), (size_t)m * 4)))
+            return rc;
+        if ((rc = copy(range.data(), at<const uint2>(const_cast<void*>(saved), L.saved_frag.range),
+                       range.size() * sizeof(uint2))))
+            return rc;
+        if ((rc = copy(zk.data(), at<const uint32_t>(const_cast<void*>(fwd_ws), L.fwd_build.zk_in), zk.size() * 4)))
+            return rc;
+        // Keys from the device's own data: the pixel that owns each sorted slot
+        // (from the per-pixel ranges) and the depth bits of the slot's point.
+        for (int64_t q = 0; q < pb.n_pixels; ++q) {
+            for (uint32_t i = range[q].x; i < range[q].y && i < m; ++i) {
+                const uint32_t vp = ids_host[i] >> 2;
+                const uint32_t zb = vp < zk.size() ? zk[vp] + pb.zbase : 0xFFFFFFFFu;
+                keys_host[i] = ((uint64_t)q << 32) | zb;
+            }
         }
+        return INPC_OK;
     }
+    // Tile lists: rebuild every pixel's splat list from the device's sorted
+    // tile entries (entries of a tile restricted to one pixel keep their order).
+    Problem pt;
+    if ((rc = make_problem(views, n_views, n_points, F, fdt, INPC_SAVE, (int)sc[1], pt))) return rc;
+    const int tsz = tile_size_of((int)sc[1]);
+    if (!fwd_ws || fwd_ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
+    std::vector<uint32_t> ent(m);
+    std::vector<uint2> range((size_t)pt.n_tiles);
+    std::vector<PointRec> rec((size_t)pb.n_vp);
+    std::vector<uint32_t> zk((size_t)pb.n_vp);
+    if ((rc = copy(ent.data(), at<const uint32_t>(const_cast<void*>(saved), L.saved_frag.ids), (size_t)m * 4)))
+        return rc;
+    if ((rc = copy(range.data(), at<const uint2>(const_cast<void*>(saved), L.saved_frag.range),
+                   range.size() * sizeof(uint2))))
+        return rc;
+    if ((rc = copy(rec.data(), at<const PointRec>(const_cast<void*>(saved), L.saved_frag.rec),
+                   rec.size() * sizeof(PointRec))))
+        return rc;
+    if ((rc = copy(zk.data(), at<const uint32_t>(const_cast<void*>(fwd_ws), L.fwd_build.zk_in), zk.size() * 4)))
+        return rc;
+    std::vector<uint32_t> count((size_t)pb.n_pixels + 1, 0);
+    auto for_each_splat = [&](auto&& emit) {
+        size_t v = 0;
+        for (int64_t t = 0; t < pt.n_tiles; ++t) {
+            while (v + 1 < pt.views.size() && pt.views[v + 1].tile_offset <= t) ++v;
+            const GpuView& V = pt.views[v];
+            const int64_t lt = t - V.tile_offset;
+            const int tx = (int)(lt % V.tiles_x), ty = (int)(lt / V.tiles_x);
+            for (uint32_t i = range[t].x; i < range[t].y && i < m; ++i) {
+                const uint32_t vp = ent[i];
+                if (vp >= rec.size()) continue;
+                const uint32_t a = rec[vp].anc;
+                const int x0 = (int)(a & 0x3FFFu) - 1, y0 = (int)((a >> 14) & 0x3FFFu) - 1;
+                for (int c = 0; c < 4; ++c) {
+                    if (!((a >> (28 + c)) & 1u)) continue;
+                    const int px = x0 + (c & 1), py = y0 + (c >> 1);
+                    if (px / tsz != tx || py / tsz != ty) continue;
+                    const int64_t q = V.pixel_offset + (int64_t)py * V.W + px;
+                    emit(q, vp, c);
+                }
+            }
+        }
+    };
+    for_each_splat([&](int64_t q, uint32_t, int) { ++count[(size_t)q + 1]; });
+    for (size_t q = 0; q < (size_t)pb.n_pixels; ++q) count[q + 1] += count[q];
+    const uint32_t total = count[(size_t)pb.n_pixels];
+    *m_out = total;
+    if (!keys_host || !ids_host || cap < (int64_t)total) return INPC_OK;
+    for_each_splat([&](int64_t q, uint32_t vp, int c) {
+        const uint32_t slot = count[(size_t)q]++;
+        ids_host[slot] = 4u * vp + (uint32_t)c;
+        keys_host[slot] = ((uint64_t)q << 32) | (zk[vp] + pb.zbase);
+    });
     return INPC_OK;
 }
 

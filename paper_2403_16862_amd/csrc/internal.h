@@ -49,9 +49,11 @@ void launch_upload_views(const GpuView* host_views, int n, GpuView* dev, hipStre
 
 void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
+// zval = vp | hb << 28 with hb the corner mask, or (tile_log2 > 0) the
+// number of 2^tile_log2-pixel square tiles the point's splats touch.
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, hipStream_t s);
+                    uint32_t* zval, int tile_log2, hipStream_t s);
 
 // Emission of the fragments of depth-sorted view points (count, scan, write).
 constexpr int kEmitBlock = 256;
@@ -60,6 +62,10 @@ size_t emit_chunks(int64_t n_vp);
 void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev,
                  uint32_t* pkey, uint32_t* pid, hipStream_t s);
+// Tile entries of depth-sorted view points: (global tile id, view point).
+void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+                      int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
+                      uint32_t* tkey, uint32_t* tval, hipStream_t s);
 
 // Stable LSD radix sort of (u32 key, u32 value) pairs over key bits
 // [0, bits).  n_dev (may be null) holds the live element count on the
@@ -123,6 +129,16 @@ void launch_appearance_bwd(const float* xyz, const float* raw, const GpuView* vi
 // Per-pixel average of K planes of ``plane`` floats each (float64 sums).
 void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipStream_t s);
 
+// Tile-list blend forward / backward (one block per tile; T_k by splat id).
+void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
+                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     float tau, float* image, float* t_final, PixelState* state, float* t_id,
+                     float* splat_weight, hipStream_t s);
+void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
+                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     float tau, const PixelState* state, const float* g_img, const float* g_t,
+                     float* t_id, int rebuild_t, float2* frec, hipStream_t s);
+
 // Per-point blend weight from the per-splat weights T alpha (indexed by splat id).
 void launch_blend_weight(int64_t n_vp, const PointRec* rec, const float* splat_weight, float* out,
                          hipStream_t s);
@@ -155,8 +171,19 @@ inline BlendShape blend_shape_dims(int shape) {
         default: return {1, 8};
     }
 }
-inline int blend_block_w(int shape) { return 2 * blend_shape_dims(shape).wxp; }
+// Tile-list blending: one block per square tile of pixels, one thread per
+// pixel (shape 5: 16x16 tiles, 256 threads; shape 6: 8x8 tiles, 64 threads).
+constexpr int kTileShape16 = 5;
+constexpr int kTileShape8 = 6;
+inline bool is_tile_shape(int shape) { return shape == kTileShape16 || shape == kTileShape8; }
+inline int tile_size_of(int shape) { return shape == kTileShape16 ? 16 : 8; }
+inline int tile_log2_of(int shape) { return shape == kTileShape16 ? 4 : 3; }
+
+inline int blend_block_w(int shape) {
+    return is_tile_shape(shape) ? tile_size_of(shape) : 2 * blend_shape_dims(shape).wxp;
+}
 inline int blend_block_h(int shape) {
+    if (is_tile_shape(shape)) return tile_size_of(shape);
     const BlendShape b = blend_shape_dims(shape);
     return 2 * (64 / b.lanes / b.wxp);
 }

@@ -51,6 +51,22 @@ void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s) {
 // The float32 operations below decide which splats exist and where, so they
 // are evaluated exactly as written: no contraction into fused multiply-adds,
 // correctly rounded division, and this association order.
+// Number of distinct 2^lg x 2^lg tiles among the pixels of the corners in mask.
+__device__ __forceinline__ uint32_t tile_entries(int x0, int y0, uint32_t mask, int lg) {
+    uint32_t t[4];
+    uint32_t n = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (!((mask >> c) & 1u)) continue;
+        const uint32_t k = ((uint32_t)((y0 + (c >> 1)) >> lg) << 16) | (uint32_t)((x0 + (c & 1)) >> lg);
+        bool dup = false;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dup |= (j < (int)n) && t[j] == k;
+        if (!dup) t[n++] = k;
+    }
+    return n;
+}
+
 __device__ __forceinline__ void project_point(const GpuView& V, float x, float y, float z,
                                               PointRec& r, uint32_t& zbits) {
 #pragma clang fp contract(off)
@@ -97,7 +113,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
                                                  int64_t n_vp, uint32_t zbase, uint32_t zkey_none,
                                                  PointRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey,
-                                                 uint32_t* __restrict__ zval) {
+                                                 uint32_t* __restrict__ zval, int tile_log2) {
     const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (vp >= n_vp) return;
     const int v = n_views == 1 ? 0
@@ -112,16 +128,18 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
     r.opa = opacity[V.attr_offset + (vp - V.vpoint_offset)];
     rec[vp] = r;
     zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
-    zval[vp] = (uint32_t)vp | (anc_mask(r.anc) << 28);
+    const uint32_t m = anc_mask(r.anc);
+    const uint32_t hb = tile_log2 ? (m ? tile_entries(anc_x0(r.anc), anc_y0(r.anc), m, tile_log2) : 0u) : m;
+    zval[vp] = (uint32_t)vp | (hb << 28);
 }
 
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, hipStream_t s) {
+                    uint32_t* zval, int tile_log2, hipStream_t s) {
     if (n_vp == 0) return;
     const int64_t blocks = (n_vp + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, xyz, opa, views, n_views,
-                       n_vp, zbase, zkey_none, rec, zkey, zval);
+                       n_vp, zbase, zkey_none, rec, zkey, zval, tile_log2);
 }
 
 // ----------------------------------------------------------------- emission
@@ -132,6 +150,14 @@ constexpr int kChunk = kEmitBlock * kEmitItems;
 
 size_t emit_chunks(int64_t n_vp) { return (size_t)((n_vp + kChunk - 1) / kChunk); }
 
+// Items per view point: the corner count (popcount of the mask) or, for tile
+// entries, the count itself.
+template <bool TILE>
+__device__ __forceinline__ uint32_t items_of(uint32_t zval) {
+    return TILE ? (zval >> 28) : (uint32_t)__popc(zval >> 28);
+}
+
+template <bool TILE>
 __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __restrict__ zval,
                                                            int64_t n_vp,
                                                            uint32_t* __restrict__ chunk_cnt) {
@@ -140,7 +166,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __res
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i)
-        if (base + i < n_vp) cnt += __popc(zval[base + i] >> 28);
+        if (base + i < n_vp) cnt += items_of<TILE>(zval[base + i]);
     uint32_t total;
     block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
     if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
@@ -217,11 +243,83 @@ void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView
         launch_fill_u32(m_dev, 0u, 1, s);
         return;
     }
-    hipLaunchKernelGGL(k_emit_count, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
+    hipLaunchKernelGGL(k_emit_count<false>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
                        n_vp, chunk_cnt);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev);
     hipLaunchKernelGGL(k_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
                        rec, views, n_views, n_vp, chunk_cnt, pkey, pid);
+}
+
+// Tile entries: one (tile, view point) pair per distinct 16x16 tile that the
+// point's splats touch, written in the order of the depth-sorted points
+// (tiles of one point in ascending corner order of first appearance).
+__global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
+    const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
+    const GpuView* __restrict__ views, int n_views, int64_t n_vp, int lg,
+    const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ tkey,
+    uint32_t* __restrict__ tval) {
+    __shared__ uint32_t s_tmp[kEmitBlock / kWave];
+    __shared__ uint32_t s_key[4 * kChunk];
+    __shared__ uint32_t s_id[4 * kChunk];
+    const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
+    uint32_t vals[kEmitItems];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i) {
+        vals[i] = (base + i < n_vp) ? zval[base + i] : 0u;
+        cnt += vals[i] >> 28;
+    }
+    uint32_t total;
+    uint32_t pos = block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
+#pragma unroll
+    for (int i = 0; i < kEmitItems; ++i) {
+        if ((vals[i] >> 28) == 0u) continue;
+        const uint32_t vp = vals[i] & kVpMask;
+        const PointRec r = rec[vp];
+        const int v = n_views == 1 ? 0
+                                   : find_view(views, n_views, (int64_t)vp,
+                                               [](const GpuView& g) { return g.vpoint_offset; });
+        const GpuView& V = views[v];
+        const int x0 = anc_x0(r.anc), y0 = anc_y0(r.anc);
+        const uint32_t mask = anc_mask(r.anc);
+        uint32_t seen[4];
+        int n = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!((mask >> c) & 1u)) continue;
+            const int tx = (x0 + (c & 1)) >> lg, ty = (y0 + (c >> 1)) >> lg;
+            const uint32_t t = (uint32_t)(V.tile_offset + (int64_t)ty * V.tiles_x + tx);
+            bool dup = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dup |= (j < n) && seen[j] == t;
+            if (dup) continue;
+            seen[n++] = t;
+            s_key[pos] = t;
+            s_id[pos] = vp;
+            ++pos;
+        }
+    }
+    __syncthreads();
+    const uint32_t off = chunk_off[blockIdx.x];
+    for (uint32_t j = threadIdx.x; j < total; j += kEmitBlock) {
+        tkey[off + j] = s_key[j];
+        tval[off + j] = s_id[j];
+    }
+}
+
+void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+                      int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
+                      uint32_t* tkey, uint32_t* tval, hipStream_t s) {
+    const size_t chunks = emit_chunks(n_vp);
+    if (chunks == 0) {
+        launch_fill_u32(m_dev, 0u, 1, s);
+        return;
+    }
+    hipLaunchKernelGGL(k_emit_count<true>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
+                       n_vp, chunk_cnt);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev);
+    hipLaunchKernelGGL(k_tile_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
+                       rec, views, n_views, n_vp, tile_log2, chunk_cnt, tkey, tval);
 }
 
 }  // namespace inpc
