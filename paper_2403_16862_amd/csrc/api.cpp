@@ -192,7 +192,8 @@ struct Carver {
 // splat ids and per-pixel ranges; it lives in ``saved`` in SAVE mode and in
 // the workspace of whichever pass builds it in RECOMPUTE mode.
 struct FragOffsets {
-    size_t rec, ids, range, tk;   // tk: T_k of every blended splat, by sorted slot
+    size_t rec, ids, range, tk;   // tk: T_k of every blended splat (by sorted slot, or by splat id)
+    size_t payload;               // record + feature row per view point (tile lists)
 };
 struct BuildOffsets {  // transient buffers of the fragment build
     size_t views, scalars, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, chunks, pk_a, pk_b, pv_other, counts;
@@ -224,6 +225,7 @@ static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
     f.ids = c.take((size_t)4 * pb.n_vp * 4);
     f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
     f.tk = c.take((size_t)4 * pb.n_vp * 4);
+    f.payload = c.take((size_t)pb.n_vp * payload_stride(pb.F, pb.fdt));
 }
 
 static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
@@ -352,7 +354,7 @@ static int resolve_tuning(int requested, const Problem& pb) {
 // splat-level sort only runs the pixel digits; together the passes form one
 // stable LSD radix sort of the 64-bit (pixel << 32 | depth) keys.
 static void build_fragments(const Problem& pb, const Tuning& tn, const float* xyz,
-                            const float* opacity, void* frag_base, const FragOffsets& fo,
+                            const float* opacity, const void* feat, void* frag_base, const FragOffsets& fo,
                             void* build_base, const BuildOffsets& bo, uint32_t* m_dev,
                             hipStream_t s) {
     GpuView* views = at<GpuView>(build_base, bo.views);
@@ -365,7 +367,9 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     {
         ProfScope p(kStProject, s);
         launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in,
-                       tile ? tile_log2_of(tn.blend_shape) : 0, s);
+                       tile ? tile_log2_of(tn.blend_shape) : 0, feat, pb.F * (pb.fdt == INPC_BF16 ? 2 : 4),
+                       tile ? at<unsigned char>(frag_base, fo.payload) : nullptr, payload_stride(pb.F, pb.fdt),
+                       s);
     }
     uint32_t* zk_a = at<uint32_t>(build_base, bo.zk_a);
     uint32_t* zv_a = at<uint32_t>(build_base, bo.zv_a);
@@ -424,7 +428,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     uint32_t* m_dev = at<uint32_t>(saved, L.s_scalars);
     void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
-    build_fragments(pb, tn, xyz, opacity, frag_base, fo, ws, L.fwd_build, m_dev, s);
+    build_fragments(pb, tn, xyz, opacity, feat, frag_base, fo, ws, L.fwd_build, m_dev, s);
     // Per-splat blend weights (indexed by splat id) reuse the pixel sort's
     // spare value buffer, which is dead once the sort has finished.
     float* splat_weight = blend_weight ? at<float>(ws, L.fwd_build.pv_other) : nullptr;
@@ -439,7 +443,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
             launch_tile_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
                             (int)pb.views.size(), pb.n_tiles,
                             at<uint2>(frag_base, fo.range), at<uint32_t>(frag_base, fo.ids),
-                            at<PointRec>(frag_base, fo.rec), feat, tau, image, t_final,
+                            at<unsigned char>(frag_base, fo.payload), payload_stride(pb.F, pb.fdt), tau, image, t_final,
                             at<PixelState>(saved, L.s_state), tk, splat_weight, s);
         else
             launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
@@ -474,7 +478,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
         fo = &L.saved_frag;
     } else {
         // Rebuild the fragment state exactly as the forward did.
-        build_fragments(pb, tn, xyz, opacity, ws, L.bwd_frag, ws, L.bwd_build,
+        build_fragments(pb, tn, xyz, opacity, feat, ws, L.bwd_frag, ws, L.bwd_build,
                         at<uint32_t>(ws, L.bwd_build.scalars), s);
         views = at<GpuView>(ws, L.bwd_build.views);
         frag_base = ws;
@@ -491,7 +495,8 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
         launch_tile_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
                         at<const uint2>(const_cast<void*>(frag_base), fo->range),
                         at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
-                        at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,
+                        at<const unsigned char>(const_cast<void*>(frag_base), fo->payload),
+                        payload_stride(pb.F, pb.fdt), tau,
                         at<const PixelState>(sv, L.s_state), g_img, g_t,
                         at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
                         frec, s);

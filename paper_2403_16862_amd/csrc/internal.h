@@ -51,9 +51,19 @@ void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
 // zval = vp | hb << 28 with hb the corner mask, or (tile_log2 > 0) the
 // number of 2^tile_log2-pixel square tiles the point's splats touch.
+// payload (may be null): per view point, the record followed by the feature
+// row (stored type), ps bytes per point, written for points with splats.
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, int tile_log2, hipStream_t s);
+                    uint32_t* zval, int tile_log2, const void* feat, int feat_row_bytes,
+                    unsigned char* payload, int ps, hipStream_t s);
+
+// Bytes per view point of the record + feature payload (64-byte multiple, so
+// that a point's payload spans as few cache lines as possible).
+inline int payload_stride(int F, int feat_dtype) {
+    const int b = 16 + F * (feat_dtype == 1 ? 2 : 4);
+    return (b + 63) / 64 * 64;
+}
 
 // Emission of the fragments of depth-sorted view points (count, scan, write).
 constexpr int kEmitBlock = 256;
@@ -131,11 +141,11 @@ void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipSt
 
 // Tile-list blend forward / backward (one block per tile; T_k by splat id).
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, float* image, float* t_final, PixelState* state, float* t_id,
                      float* splat_weight, hipStream_t s);
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
                      float* t_id, int rebuild_t, float2* frec, hipStream_t s);
 

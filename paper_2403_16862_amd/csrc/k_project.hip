@@ -113,33 +113,86 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
                                                  int64_t n_vp, uint32_t zbase, uint32_t zkey_none,
                                                  PointRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey,
-                                                 uint32_t* __restrict__ zval, int tile_log2) {
-    const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (vp >= n_vp) return;
-    const int v = n_views == 1 ? 0
-                               : find_view(views, n_views, vp,
-                                           [](const GpuView& g) { return g.vpoint_offset; });
-    const GpuView& V = views[v];
-    const int64_t p = V.point_offset + (vp - V.vpoint_offset);
-    const float x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
-    PointRec r;
-    uint32_t zb;
-    project_point(V, x, y, z, r, zb);
-    r.opa = opacity[V.attr_offset + (vp - V.vpoint_offset)];
-    rec[vp] = r;
-    zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
-    const uint32_t m = anc_mask(r.anc);
-    const uint32_t hb = tile_log2 ? (m ? tile_entries(anc_x0(r.anc), anc_y0(r.anc), m, tile_log2) : 0u) : m;
-    zval[vp] = (uint32_t)vp | (hb << 28);
+                                                 uint32_t* __restrict__ zval, int tile_log2,
+                                                 const unsigned char* __restrict__ feat, int frow,
+                                                 unsigned char* __restrict__ payload, int ps) {
+    __shared__ PointRec s_rec[256];
+    __shared__ int64_t s_row[256];   // feature row of the view point, -1 when no payload is due
+    const int64_t vp0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t vp = vp0 + threadIdx.x;
+    int64_t arow = -1;
+    PointRec r{};
+    if (vp < n_vp) {
+        const int v = n_views == 1 ? 0
+                                   : find_view(views, n_views, vp,
+                                               [](const GpuView& g) { return g.vpoint_offset; });
+        const GpuView& V = views[v];
+        const int64_t p = V.point_offset + (vp - V.vpoint_offset);
+        const float x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
+        uint32_t zb;
+        project_point(V, x, y, z, r, zb);
+        arow = V.attr_offset + (vp - V.vpoint_offset);
+        r.opa = opacity[arow];
+        rec[vp] = r;
+        zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
+        const uint32_t m = anc_mask(r.anc);
+        const uint32_t hb = tile_log2 ? (m ? tile_entries(anc_x0(r.anc), anc_y0(r.anc), m, tile_log2) : 0u) : m;
+        zval[vp] = (uint32_t)vp | (hb << 28);
+        if (!m) arow = -1;
+    }
+    if (!payload) return;
+    if ((frow & 15) == 0) {
+        // The block's payload rows are one contiguous run: write it with
+        // consecutive threads on consecutive 16-byte pieces (record from LDS,
+        // feature pieces straight from the feature rows).
+        s_rec[threadIdx.x] = r;
+        s_row[threadIdx.x] = arow;
+        __syncthreads();
+        const int64_t rows64 = n_vp - vp0;
+        const int rows = rows64 < 256 ? (int)rows64 : 256;
+        // Whole 16-byte pieces of every due row are written, padding included
+        // (zeros), so no cache line of the payload is left partly written.
+        const int cpr = ps / 16, fcs = frow / 16;
+        uint4* dst = reinterpret_cast<uint4*>(payload + (size_t)vp0 * ps);
+        auto piece = [&](int row, int col) -> uint4 {
+            if (col == 0) return *reinterpret_cast<const uint4*>(&s_rec[row]);
+            if (col <= fcs) return reinterpret_cast<const uint4*>(feat + (size_t)s_row[row] * frow)[col - 1];
+            return make_uint4(0u, 0u, 0u, 0u);
+        };
+        if ((256 % cpr) == 0) {
+            const int col = threadIdx.x % cpr, rstep = 256 / cpr;
+            for (int row = threadIdx.x / cpr; row < rows; row += rstep)
+                if (s_row[row] >= 0) dst[row * cpr + col] = piece(row, col);
+        } else {
+            for (int k = threadIdx.x; k < rows * cpr; k += 256) {
+                const int row = k / cpr, col = k - row * cpr;
+                if (s_row[row] >= 0) dst[k] = piece(row, col);
+            }
+        }
+    } else if (arow >= 0) {
+        unsigned char* d = payload + (size_t)vp * ps;
+        reinterpret_cast<PointRec*>(d)[0] = r;
+        const unsigned char* src = feat + (size_t)arow * frow;
+        d += sizeof(PointRec);
+        if ((frow & 3) == 0) {
+            for (int b = 0; b < frow; b += 4)
+                *reinterpret_cast<uint32_t*>(d + b) = *reinterpret_cast<const uint32_t*>(src + b);
+        } else {
+            for (int b = 0; b < frow; b += 2)
+                *reinterpret_cast<uint16_t*>(d + b) = *reinterpret_cast<const uint16_t*>(src + b);
+        }
+    }
 }
 
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, int tile_log2, hipStream_t s) {
+                    uint32_t* zval, int tile_log2, const void* feat, int feat_row_bytes,
+                    unsigned char* payload, int ps, hipStream_t s) {
     if (n_vp == 0) return;
     const int64_t blocks = (n_vp + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, xyz, opa, views, n_views,
-                       n_vp, zbase, zkey_none, rec, zkey, zval, tile_log2);
+                       n_vp, zbase, zkey_none, rec, zkey, zval, tile_log2,
+                       reinterpret_cast<const unsigned char*>(feat), feat_row_bytes, payload, ps);
 }
 
 // ----------------------------------------------------------------- emission

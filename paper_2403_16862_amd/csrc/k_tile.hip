@@ -83,17 +83,38 @@ struct EntryRegs {
     float4 t4;
 };
 
+// Feature row stored after the 16-byte record in a payload row (16-byte aligned).
+template <typename FT, int FM, bool DYN>
+__device__ __forceinline__ void payload_feat(const FT* __restrict__ row, int Fd, float (&c)[FM]) {
+    if constexpr (!DYN) {
+        load_row<FM>(row, c);
+    } else {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            if (f < Fd) {
+                if constexpr (sizeof(FT) == 4) c[f] = reinterpret_cast<const float*>(row)[f];
+                else c[f] = bf16_to_f32(reinterpret_cast<const uint16_t*>(row)[f]);
+            } else {
+                c[f] = 0.0f;
+            }
+        }
+    }
+}
+
+// Gathers one entry: its view point, and the point's record and feature row
+// from the co-located payload (one or two cache lines per point).
 template <typename FT, int FM, bool DYN, bool WANT_T>
 __device__ __forceinline__ void fetch_entry(EntryRegs<FM>& e, uint32_t c0, uint32_t end,
-                                            const uint32_t* __restrict__ vals, const PointRec* __restrict__ rec,
-                                            const FT* __restrict__ feat, int64_t fbase, int Fd,
+                                            const uint32_t* __restrict__ vals,
+                                            const unsigned char* __restrict__ payload, int ps, int Fd,
                                             const float* __restrict__ t_id) {
     const uint32_t j = c0 + threadIdx.x;
     e.valid = c0 < end && j < end;
     if (e.valid) {
         e.vp = vals[j];
-        e.r = rec[e.vp];
-        feat_row<FT, FM, DYN>(feat, fbase + e.vp, Fd, e.cf);
+        const unsigned char* row = payload + (size_t)e.vp * ps;
+        e.r = *reinterpret_cast<const PointRec*>(row);
+        payload_feat<FT, FM, DYN>(reinterpret_cast<const FT*>(row + sizeof(PointRec)), Fd, e.cf);
         if constexpr (WANT_T) e.t4 = reinterpret_cast<const float4*>(t_id)[e.vp];
     }
 }
@@ -152,14 +173,13 @@ __device__ __forceinline__ uint32_t cover_word(const TileChunk<TS, FM>& S, int w
 template <typename FT, int FM, bool DYN, int TS>
 __global__ __launch_bounds__(TS * TS) void k_tile_fwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
-    const uint32_t* __restrict__ vals, const PointRec* __restrict__ rec, const FT* __restrict__ feat, int Fd,
+    const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, float* __restrict__ image, float* __restrict__ t_final, PixelState* __restrict__ state,
     float* __restrict__ t_id, float* __restrict__ splat_weight) {
     constexpr int FS = TileChunk<TS, FM>::FS, NT = TileDims<TS>::NT, NW = TileDims<TS>::NW;
     __shared__ TileChunk<TS, FM> S;
     const TileCtx c = tile_ctx<TS>(views, n_views);
     const uint2 r = range[c.tile];
-    const int64_t fbase = c.V->attr_offset - c.V->vpoint_offset;
     float C[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) C[f] = 0.0f;
@@ -167,13 +187,13 @@ __global__ __launch_bounds__(TS * TS) void k_tile_fwd(
     uint32_t nb = 0, last = 0;
     bool done = !c.inside;
     EntryRegs<FM> e;
-    fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, rec, feat, fbase, Fd, nullptr);
+    fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
     for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
         clear_bits<TS, FM>(S);
         __syncthreads();
         store_entry<TS, FM, false>(S, c, e);
         __syncthreads();
-        fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, rec, feat, fbase, Fd, nullptr);
+        fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
         if (!done) {
             const int lim = (int)(r.y - c0);
 #pragma unroll
@@ -215,7 +235,7 @@ __global__ __launch_bounds__(TS * TS) void k_tile_fwd(
 template <typename FT, int FM, bool DYN, int TS>
 __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
-    const uint32_t* __restrict__ vals, const PointRec* __restrict__ rec, const FT* __restrict__ feat, int Fd,
+    const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, const PixelState* __restrict__ state, const float* __restrict__ g_img,
     const float* __restrict__ g_t, float* __restrict__ t_id, int rebuild_t, float2* __restrict__ frec) {
     constexpr int FS = TileChunk<TS, FM>::FS, NT = TileDims<TS>::NT, NW = TileDims<TS>::NW;
@@ -223,7 +243,6 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
     __shared__ uint32_t s_last;
     const TileCtx c = tile_ctx<TS>(views, n_views);
     const uint2 r = range[c.tile];
-    const int64_t fbase = c.V->attr_offset - c.V->vpoint_offset;
     const uint32_t last = c.inside ? state[c.q].pad0 : 0u;
     if (threadIdx.x == 0) s_last = 0u;
     __syncthreads();
@@ -233,13 +252,13 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
         float T = 1.0f;
         bool done = !c.inside;
         EntryRegs<FM> e;
-        fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, rec, feat, fbase, Fd, nullptr);
+        fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
         for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
             clear_bits<TS, FM>(S);
             __syncthreads();
             store_entry<TS, FM, false>(S, c, e);
             __syncthreads();
-            fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, rec, feat, fbase, Fd, nullptr);
+            fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
             if (!done) {
                 const int lim = (int)(r.y - c0);
 #pragma unroll
@@ -277,7 +296,7 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
     }
     const uint32_t n_chunks = (lmax - r.x + NT - 1) / NT;
     EntryRegs<FM> e;
-    fetch_entry<FT, FM, DYN, true>(e, r.x + (n_chunks - 1) * NT, r.y, vals, rec, feat, fbase, Fd, t_id);
+    fetch_entry<FT, FM, DYN, true>(e, r.x + (n_chunks - 1) * NT, r.y, vals, payload, ps, Fd, t_id);
     for (int k = (int)n_chunks - 1; k >= 0; --k) {
         const uint32_t c0 = r.x + (uint32_t)k * NT;
         __syncthreads();   // the previous chunk's LDS reads are done
@@ -286,7 +305,7 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
         store_entry<TS, FM, true>(S, c, e);
         __syncthreads();
         if (k > 0)
-            fetch_entry<FT, FM, DYN, true>(e, c0 - NT, r.y, vals, rec, feat, fbase, Fd, t_id);
+            fetch_entry<FT, FM, DYN, true>(e, c0 - NT, r.y, vals, payload, ps, Fd, t_id);
         if (last > c0) {
             const int lim = (int)(last - c0);
 #pragma unroll
@@ -316,35 +335,35 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
 
 template <typename FT, int FM, bool DYN, int TS>
 static void tile_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
-                       const PointRec* rec, const void* feat, int Fd, float tau, float* image, float* t_final,
+                       const unsigned char* payload, int ps, int Fd, float tau, float* image, float* t_final,
                        PixelState* state, float* t_id, float* splat_weight, hipStream_t s) {
     hipLaunchKernelGGL((k_tile_fwd<FT, FM, DYN, TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, s, views, n_views,
-                       range, vals, rec, reinterpret_cast<const FT*>(feat), Fd, tau, image, t_final, state, t_id,
+                       range, vals, payload, ps, Fd, tau, image, t_final, state, t_id,
                        splat_weight);
 }
 
 template <typename FT, int FM, bool DYN, int TS>
 static void tile_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
-                       const PointRec* rec, const void* feat, int Fd, float tau, const PixelState* state,
+                       const unsigned char* payload, int ps, int Fd, float tau, const PixelState* state,
                        const float* g_img, const float* g_t, float* t_id, int rebuild_t, float2* frec,
                        hipStream_t s) {
     hipLaunchKernelGGL((k_tile_bwd<FT, FM, DYN, TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, s, views, n_views,
-                       range, vals, rec, reinterpret_cast<const FT*>(feat), Fd, tau, state, g_img, g_t, t_id,
+                       range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_id,
                        rebuild_t, frec);
 }
 
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, float* image, float* t_final, PixelState* state, float* t_id,
                      float* splat_weight, hipStream_t s) {
     if (n_tiles == 0) return;
     auto go = [&]<int TS>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_fwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, rec, feat, F, tau,
+                tile_fwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
                                                         image, t_final, state, t_id, splat_weight, s);
             else
-                tile_fwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, rec, feat, F, tau, image,
+                tile_fwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, image,
                                                t_final, state, t_id, splat_weight, s);
         });
     };
@@ -353,17 +372,17 @@ void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int
 }
 
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const PointRec* rec, const void* feat,
+                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
                      float* t_id, int rebuild_t, float2* frec, hipStream_t s) {
     if (n_tiles == 0) return;
     auto go = [&]<int TS>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_bwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, rec, feat, F, tau,
+                tile_bwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
                                                         state, g_img, g_t, t_id, rebuild_t, frec, s);
             else
-                tile_bwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, rec, feat, F, tau, state,
+                tile_bwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, state,
                                                g_img, g_t, t_id, rebuild_t, frec, s);
         });
     };
