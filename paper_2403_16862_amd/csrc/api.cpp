@@ -21,9 +21,12 @@ namespace inpc {
 // zdigit / pdigit = 0: choose the digit width from the key width (fewest
 // passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
+    {0, 0, 16, kTileShape8x2, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, 2 lanes/pixel"},
     {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
     {0, 0, 32, kTileShape8, kTileShape8, "auto digits, 8192-key tiles, tile-list blend 8x8 (entries per tile)"},
     {0, 0, 16, kTileShape16, kTileShape16, "auto digits, 4096-key tiles, tile-list blend 16x16 (entries per tile)"},
+    {0, 0, 16, kTileShape8x4, kTileShape8x4, "auto digits, 4096-key tiles, tile-list blend 8x8, 4 lanes/pixel"},
+    {0, 0, 16, kTileShape8x4, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 4 lanes/pixel, bwd 1"},
     {0, 0, 16, 3, 4, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
     {0, 0, 16, 3, 3, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 8 lanes/pixel 4x2"},
     {0, 0, 16, 4, 4, "auto digits, 4096-key tiles, blend fwd 16 lanes/pixel 2x2, bwd 16 lanes/pixel 2x2"},
@@ -489,10 +492,11 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
         ProfScope p(kStClearRecords, s);
         launch_fill_u32(reinterpret_cast<uint32_t*>(frec), 0u, (size_t)8 * pb.n_vp, s);
     }
+    const int bshape = bwd_shape_of(tid, pb.mode);
     {
     ProfScope p(kStBlendBwd, s);
-    if (is_tile_shape(bwd_shape_of(tid, pb.mode)))
-        launch_tile_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
+    if (is_tile_shape(bshape))
+        launch_tile_bwd(pb.F, pb.fdt, bshape, views, (int)pb.views.size(), pb.n_tiles,
                         at<const uint2>(const_cast<void*>(frag_base), fo->range),
                         at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
                         at<const unsigned char>(const_cast<void*>(frag_base), fo->payload),
@@ -501,7 +505,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
                         at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
                         frec, s);
     else
-        launch_blend_bwd(pb.F, pb.fdt, bwd_shape_of(tid, pb.mode), views, (int)pb.views.size(), pb.n_tiles,
+        launch_blend_bwd(pb.F, pb.fdt, bshape, views, (int)pb.views.size(), pb.n_tiles,
                          at<const uint2>(const_cast<void*>(frag_base), fo->range),
                          at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
                          at<const PointRec>(const_cast<void*>(frag_base), fo->rec), feat, tau,

@@ -181,11 +181,15 @@ inline BlendShape blend_shape_dims(int shape) {
         default: return {1, 8};
     }
 }
-// Tile-list blending: one block per square tile of pixels, one thread per
-// pixel (shape 5: 16x16 tiles, 256 threads; shape 6: 8x8 tiles, 64 threads).
+// Tile-list blending: one block per square tile of pixels with L lanes per
+// pixel (shape 5: 16x16 tiles, 1 lane, 256 threads; shape 6: 8x8 tiles,
+// 1 lane, 64 threads; shape 7: 8x8 tiles, 4 lanes, 256 threads; shape 8:
+// 8x8 tiles, 2 lanes, 128 threads).
 constexpr int kTileShape16 = 5;
 constexpr int kTileShape8 = 6;
-inline bool is_tile_shape(int shape) { return shape == kTileShape16 || shape == kTileShape8; }
+constexpr int kTileShape8x4 = 7;
+constexpr int kTileShape8x2 = 8;
+inline bool is_tile_shape(int shape) { return shape >= kTileShape16 && shape <= kTileShape8x2; }
 inline int tile_size_of(int shape) { return shape == kTileShape16 ? 16 : 8; }
 inline int tile_log2_of(int shape) { return shape == kTileShape16 ? 4 : 3; }
 

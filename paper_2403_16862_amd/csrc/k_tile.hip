@@ -5,24 +5,30 @@
 // tile (16x16 or 8x8 pixels): one entry per (tile, point) pair for every tile
 // the point's 2x2 footprint touches (about 1.13 or 1.27 entries per point),
 // sorted stably by tile after the depth sort, so each tile's entries are in
-// front-to-back order.  One block owns a tile, one thread per pixel.  The
+// front-to-back order.  One block owns a tile, with L lanes per pixel.  The
 // block walks its entries in chunks of one entry per thread: each thread
-// gathers one entry's point record and feature row (independent gathers, issued while
-// the previous chunk is being blended), stores it into LDS and marks the
-// pixels the entry covers in a per-pixel bit set; every thread then blends
-// the covering entries of its pixel in order, from LDS.  Restricted to one pixel, the entry order is the (depth,
-// point) order of that pixel's splats, so the result is the per-pixel
-// definition exactly; with one thread per pixel the float32 operations are
-// those of the one-lane-per-pixel list blend.
+// reads one entry's point record and feature row (one payload row laid out
+// by the projection; issued while the previous chunk is being blended),
+// stores it into LDS and marks the pixels the entry covers in a per-pixel
+// bit set.  With one lane per pixel, each thread then walks the set bits of
+// its pixel in order; with L lanes, the lanes of a pixel first turn its bits
+// into an ordered list of entry slots and then take L entries at a time,
+// with the transmittance in front of each from a prefix product of
+// 1 - alpha across the group (the grouped step of the per-pixel-list
+// blend).  Restricted to one pixel, the entry order is the (depth, point)
+// order of that pixel's splats, so the result is the per-pixel definition;
+// with one lane per pixel the float32 operations are exactly those of the
+// one-lane-per-pixel list blend.
 #include "blend_common.h"
 
 namespace inpc {
 
-// TS x TS pixels per tile, TS * TS threads per block, one chunk = one entry
-// per thread; NW words of entry bits per pixel.
-template <int TS>
+// TS x TS pixels per tile, L lanes per pixel, NT = TS * TS * L threads per
+// block; one chunk = one entry per thread; NW words of entry bits per pixel.
+template <int TS, int L>
 struct TileDims {
-    static constexpr int NT = TS * TS;
+    static constexpr int NPIX = TS * TS;
+    static constexpr int NT = NPIX * L;
     static constexpr int NW = NT / 32;
 };
 
@@ -30,12 +36,14 @@ struct TileCtx {
     const GpuView* V;
     uint32_t tile;     // global tile index
     int tx, ty;        // tile coordinates in its view
-    int lx, ly;        // pixel inside the tile
+    int pix;           // pixel inside the tile (row-major)
+    int lx, ly;
+    int sub;           // lane within the pixel's group of L
     bool inside;
     int64_t q;         // packed pixel index
 };
 
-template <int TS>
+template <int TS, int L>
 __device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, int n_views) {
     TileCtx c;
     c.tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -46,8 +54,10 @@ __device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, i
     const int64_t lt = (int64_t)c.tile - c.V->tile_offset;
     c.tx = (int)(lt % c.V->tiles_x);
     c.ty = (int)(lt / c.V->tiles_x);
-    c.lx = threadIdx.x % TS;
-    c.ly = threadIdx.x / TS;
+    c.pix = (int)threadIdx.x / L;
+    c.sub = (int)threadIdx.x % L;
+    c.lx = c.pix % TS;
+    c.ly = c.pix / TS;
     const int x = c.tx * TS + c.lx, y = c.ty * TS + c.ly;
     c.inside = x < c.V->W && y < c.V->H;
     c.q = c.V->pixel_offset + (int64_t)y * c.V->W + x;
@@ -57,19 +67,23 @@ __device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, i
 // LDS image of one chunk of entries: packed anchor word (tile-local x0+1,
 // y0+1, corner mask; 0 = no entry), record fields, feature rows at an odd
 // stride (entries read by different lanes then fall in different banks),
-// the forward's T_k of the entry's four splats (backward only), and for
-// every pixel of the tile a bit per chunk entry that covers it.
-template <int TS, int FM>
+// the forward's T_k of the entry's four splats (backward only), for every
+// pixel of the tile a bit per chunk entry that covers it, and (L > 1) every
+// pixel's covering entry slots in order, at a row stride of NT + 4 bytes.
+template <int TS, int L, int FM>
 struct TileChunk {
-    static constexpr int NT = TileDims<TS>::NT;
-    static constexpr int FS = FM | 1;                   // odd row stride in floats
-    static constexpr int BW = TileDims<TS>::NW + 1;     // words per pixel row of bits (odd stride)
+    static constexpr int NT = TileDims<TS, L>::NT;
+    static constexpr int NPIX = TileDims<TS, L>::NPIX;
+    static constexpr int FS = FM | 1;                    // odd row stride in floats
+    static constexpr int BW = TileDims<TS, L>::NW + 1;   // words per pixel row of bits (odd stride)
+    static constexpr int LS = L > 1 ? NT + 4 : 0;        // bytes per pixel row of entry slots
     uint32_t hit[NT];
     float ax[NT], ay[NT], opa[NT];
     uint32_t vp[NT];
     float feat[NT * FS];
     float4 tk[NT];
-    uint32_t bits[NT * BW];
+    uint32_t bits[NPIX * BW];
+    unsigned char lst[NPIX * LS + 4];
 };
 
 // One entry held in registers between its gather and its store into LDS,
@@ -121,9 +135,9 @@ __device__ __forceinline__ void fetch_entry(EntryRegs<FM>& e, uint32_t c0, uint3
 
 // Thread i stores its entry and marks the (at most four) pixels of the tile
 // its splats cover; ``bits`` must be cleared before.
-template <int TS, int FM, bool WANT_T>
-__device__ __forceinline__ void store_entry(TileChunk<TS, FM>& S, const TileCtx& c, const EntryRegs<FM>& e) {
-    constexpr int FS = TileChunk<TS, FM>::FS, BW = TileChunk<TS, FM>::BW;
+template <int TS, int L, int FM, bool WANT_T>
+__device__ __forceinline__ void store_entry(TileChunk<TS, L, FM>& S, const TileCtx& c, const EntryRegs<FM>& e) {
+    constexpr int FS = TileChunk<TS, L, FM>::FS, BW = TileChunk<TS, L, FM>::BW;
     const int i = threadIdx.x;
     uint32_t w = 0;
     if (e.valid) {
@@ -147,11 +161,12 @@ __device__ __forceinline__ void store_entry(TileChunk<TS, FM>& S, const TileCtx&
     S.hit[i] = w;
 }
 
-template <int TS, int FM>
-__device__ __forceinline__ void clear_bits(TileChunk<TS, FM>& S) {
-    constexpr int BW = TileChunk<TS, FM>::BW;
+template <int TS, int L, int FM>
+__device__ __forceinline__ void clear_bits(TileChunk<TS, L, FM>& S) {
+    constexpr int NT = TileDims<TS, L>::NT, N = TileChunk<TS, L, FM>::NPIX * TileChunk<TS, L, FM>::BW;
 #pragma unroll
-    for (int k = 0; k < BW; ++k) S.bits[threadIdx.x * BW + k] = 0u;
+    for (int k = 0; k < (N + NT - 1) / NT; ++k)
+        if (k * NT + (int)threadIdx.x < N) S.bits[k * NT + threadIdx.x] = 0u;
 }
 
 // Corner of entry word w whose pixel is (lx, ly) (the entry covers it).
@@ -160,124 +175,242 @@ __device__ __forceinline__ int corner_of(uint32_t w, int lx, int ly) {
     return (dy << 1) | dx;
 }
 
-// Bits of the entries j < lim of this chunk that cover the thread's pixel.
-template <int TS, int FM>
-__device__ __forceinline__ uint32_t cover_word(const TileChunk<TS, FM>& S, int wd, int lim) {
-    uint32_t m = S.bits[threadIdx.x * TileChunk<TS, FM>::BW + wd];
+// Keeps the bits of the entries j < lim of word wd.
+__device__ __forceinline__ uint32_t below_lim(uint32_t m, int wd, int lim) {
     const int lo = wd * 32;
-    if (lim <= lo) m = 0u;
-    else if (lim < lo + 32) m &= (1u << (lim - lo)) - 1u;
+    if (lim <= lo) return 0u;
+    if (lim < lo + 32) return m & ((1u << (lim - lo)) - 1u);
     return m;
 }
 
-template <typename FT, int FM, bool DYN, int TS>
-__global__ __launch_bounds__(TS * TS) void k_tile_fwd(
+// Bits of the entries j < lim of this chunk that cover the thread's pixel.
+template <int TS, int L, int FM>
+__device__ __forceinline__ uint32_t cover_word(const TileChunk<TS, L, FM>& S, const TileCtx& c, int wd, int lim) {
+    return below_lim(S.bits[c.pix * TileChunk<TS, L, FM>::BW + wd], wd, lim);
+}
+
+// L > 1: the lanes of a pixel turn its cover bits of the entries j < lim
+// into the ordered list of those entry slots (each lane takes NW / L words,
+// placed by an exclusive prefix of their bit counts across the group) and
+// clear every bit word of the pixel.  Returns the list length.
+template <int TS, int L, int FM>
+__device__ __forceinline__ int compact_cover(TileChunk<TS, L, FM>& S, const TileCtx& c, int lim) {
+    constexpr int NW = TileDims<TS, L>::NW, WPL = NW / L, BW = TileChunk<TS, L, FM>::BW;
+    static_assert(NW % L == 0 && TileDims<TS, L>::NT <= 256, "slot lists hold byte indices");
+    uint32_t w[WPL];
+    int cnt = 0;
+#pragma unroll
+    for (int t = 0; t < WPL; ++t) {
+        const int wd = c.sub * WPL + t;
+        uint32_t* b = &S.bits[c.pix * BW + wd];
+        w[t] = below_lim(*b, wd, lim);
+        *b = 0u;
+        cnt += __popc(w[t]);
+    }
+    int inc = cnt;
+#pragma unroll
+    for (int d = 1; d < L; d <<= 1) {
+        const int t = __shfl_up(inc, d, L);
+        if (c.sub >= d) inc += t;
+    }
+    const int total = __shfl(inc, L - 1, L);
+    unsigned char* out = S.lst + c.pix * TileChunk<TS, L, FM>::LS + (inc - cnt);
+#pragma unroll
+    for (int t = 0; t < WPL; ++t) {
+        uint32_t m = w[t];
+        while (m != 0u) {
+            *out++ = (unsigned char)((c.sub * WPL + t) * 32 + (__ffs(m) - 1));
+            m &= m - 1u;
+        }
+    }
+    return total;
+}
+
+// Forward state of the thread's pixel across the chunks of its tile.
+template <int FM>
+struct FwdAcc {
+    float C[FM];       // this lane's share of the colour
+    float T;
+    uint32_t nb;       // splats blended
+    uint32_t last;     // one past the last blended entry of the tile range (0: none)
+    bool done, started;
+};
+
+template <int FM>
+__device__ __forceinline__ void fwd_init(FwdAcc<FM>& a, bool done) {
+#pragma unroll
+    for (int f = 0; f < FM; ++f) a.C[f] = 0.0f;
+    a.T = 1.0f;
+    a.nb = 0u;
+    a.last = 0u;
+    a.done = done;
+    a.started = false;
+}
+
+// Blends the chunk's entries j < lim that cover the thread's pixel, in order.
+// L == 1: walks the pixel's bits (the one-lane float32 recurrence, operation
+// for operation); L > 1: takes the n slots listed by compact_cover L at a
+// time with the grouped transmittance step.  COLOUR: accumulate the colour
+// and write the per-splat weights T_k alpha_k; T_k goes to t_id if given.
+template <int TS, int L, int FM, bool COLOUR>
+__device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const TileCtx& c, uint32_t c0, int lim,
+                                            int n, float tau, FwdAcc<FM>& a, float* __restrict__ t_id,
+                                            float* __restrict__ splat_weight) {
+    constexpr int FS = TileChunk<TS, L, FM>::FS, NW = TileDims<TS, L>::NW;
+    if constexpr (L == 1) {
+#pragma unroll
+        for (int wd = 0; wd < NW; ++wd) {
+            uint32_t m = cover_word<TS, L, FM>(S, c, wd, lim);
+            while (m != 0u && !a.done) {
+                const int j = wd * 32 + (__ffs(m) - 1);
+                m &= m - 1u;
+                const int corner = corner_of(S.hit[j], c.lx, c.ly);
+                float wx, wy, alpha, om;
+                corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
+                splat_alpha(S.opa[j], wx, wy, alpha, om);
+                const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
+                if constexpr (COLOUR) {
+                    const float ta = a.T * alpha;
+#pragma unroll
+                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
+                    if (splat_weight) splat_weight[id] = ta;
+                }
+                if (t_id) t_id[id] = a.T;
+                a.T = a.T * om;
+                ++a.nb;
+                a.last = c0 + (uint32_t)j + 1u;
+                if (a.T < tau) a.done = true;
+            }
+        }
+    } else {
+        const unsigned char* lst = S.lst + c.pix * TileChunk<TS, L, FM>::LS;
+        for (int base = 0; base < n && !a.done; base += L) {
+            const int k = base + c.sub;
+            const bool valid = k < n;
+            const int j = valid ? (int)lst[k] : 0;
+            float alpha = 0.0f, om = 1.0f;
+            int corner = 0;
+            if (valid) {
+                corner = corner_of(S.hit[j], c.lx, c.ly);
+                float wx, wy;
+                corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
+                splat_alpha(S.opa[j], wx, wy, alpha, om);
+            }
+            const GroupStep g = group_step<L>(a.T, om, valid, !a.started && c.sub == 0, tau, c.sub);
+            a.started = true;
+            if (g.blended) {
+                const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
+                if constexpr (COLOUR) {
+                    const float ta = g.tb * alpha;
+#pragma unroll
+                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
+                    if (splat_weight) splat_weight[id] = ta;
+                }
+                if (t_id) t_id[id] = g.tb;
+            }
+            // the blended lanes are a prefix of the group, in list order
+            const int gbase = __lane_id() - c.sub;
+            const uint32_t mine = (uint32_t)((__ballot(g.blended) >> gbase) & ((1ull << L) - 1ull));
+            if (mine) {
+                a.nb += (uint32_t)__popc(mine);
+                a.last = c0 + (uint32_t)__shfl(j, 31 - __clz(mine), L) + 1u;
+            }
+            a.T = g.t_next;
+            if (g.done) a.done = true;
+        }
+    }
+}
+
+template <typename FT, int FM, bool DYN, int TS, int L>
+__global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, float* __restrict__ image, float* __restrict__ t_final, PixelState* __restrict__ state,
     float* __restrict__ t_id, float* __restrict__ splat_weight) {
-    constexpr int FS = TileChunk<TS, FM>::FS, NT = TileDims<TS>::NT, NW = TileDims<TS>::NW;
-    __shared__ TileChunk<TS, FM> S;
-    const TileCtx c = tile_ctx<TS>(views, n_views);
+    constexpr int NT = TileDims<TS, L>::NT;
+    __shared__ TileChunk<TS, L, FM> S;
+    const TileCtx c = tile_ctx<TS, L>(views, n_views);
     const uint2 r = range[c.tile];
-    float C[FM];
-#pragma unroll
-    for (int f = 0; f < FM; ++f) C[f] = 0.0f;
-    float T = 1.0f;
-    uint32_t nb = 0, last = 0;
-    bool done = !c.inside;
+    FwdAcc<FM> a;
+    fwd_init(a, !c.inside);
     EntryRegs<FM> e;
     fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
-    for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
-        clear_bits<TS, FM>(S);
+    if constexpr (L > 1) {
+        // from here on compact_cover clears the bits it has read
+        clear_bits<TS, L, FM>(S);
         __syncthreads();
-        store_entry<TS, FM, false>(S, c, e);
+    }
+    for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
+        if constexpr (L == 1) {
+            clear_bits<TS, L, FM>(S);
+            __syncthreads();
+        }
+        store_entry<TS, L, FM, false>(S, c, e);
         __syncthreads();
         fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
-        if (!done) {
-            const int lim = (int)(r.y - c0);
-#pragma unroll
-            for (int wd = 0; wd < NW; ++wd) {
-                uint32_t m = cover_word<TS, FM>(S, wd, lim);
-                while (m != 0u && !done) {
-                    const int j = wd * 32 + (__ffs(m) - 1);
-                    m &= m - 1u;
-                    const int corner = corner_of(S.hit[j], c.lx, c.ly);
-                    float wx, wy, alpha, om;
-                    corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
-                    splat_alpha(S.opa[j], wx, wy, alpha, om);
-                    const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
-                    const float ta = T * alpha;
-#pragma unroll
-                    for (int f = 0; f < FM; ++f) C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], C[f]);
-                    if (t_id) t_id[id] = T;
-                    if (splat_weight) splat_weight[id] = ta;
-                    T = T * om;
-                    ++nb;
-                    last = c0 + (uint32_t)j + 1u;
-                    if (T < tau) done = true;
-                }
-            }
+        const int lim = (int)(r.y - c0);
+        int n = 0;
+        if constexpr (L > 1) {
+            n = compact_cover<TS, L, FM>(S, c, lim);
+            __syncthreads();
         }
-        if (__syncthreads_and(done ? 1 : 0)) break;
+        if (!a.done) blend_chunk<TS, L, FM, true>(S, c, c0, lim, n, tau, a, t_id, splat_weight);
+        if (__syncthreads_and(a.done ? 1 : 0)) break;
     }
-    if (c.inside) {
-        f32_store<FM, DYN>(image, c.q, Fd, C);
-        t_final[c.q] = T;
+#pragma unroll
+    for (int mm = L / 2; mm >= 1; mm >>= 1) {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) a.C[f] += __shfl_xor(a.C[f], mm, L);
+    }
+    if (c.inside && c.sub == 0) {
+        f32_store<FM, DYN>(image, c.q, Fd, a.C);
+        t_final[c.q] = a.T;
         PixelState st;
-        st.n_blended = nb;
-        st.pad0 = last;   // one past the last blended entry (0: none)
+        st.n_blended = a.nb;
+        st.pad0 = a.last;
         st.pad1 = st.pad2 = 0;
         state[c.q] = st;
     }
 }
 
-template <typename FT, int FM, bool DYN, int TS>
-__global__ __launch_bounds__(TS * TS) void k_tile_bwd(
+template <typename FT, int FM, bool DYN, int TS, int L>
+__global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, const PixelState* __restrict__ state, const float* __restrict__ g_img,
     const float* __restrict__ g_t, float* __restrict__ t_id, int rebuild_t, float2* __restrict__ frec) {
-    constexpr int FS = TileChunk<TS, FM>::FS, NT = TileDims<TS>::NT, NW = TileDims<TS>::NW;
-    __shared__ TileChunk<TS, FM> S;
+    constexpr int FS = TileChunk<TS, L, FM>::FS, NT = TileDims<TS, L>::NT, NW = TileDims<TS, L>::NW;
+    __shared__ TileChunk<TS, L, FM> S;
     __shared__ uint32_t s_last;
-    const TileCtx c = tile_ctx<TS>(views, n_views);
+    const TileCtx c = tile_ctx<TS, L>(views, n_views);
     const uint2 r = range[c.tile];
     const uint32_t last = c.inside ? state[c.q].pad0 : 0u;
     if (threadIdx.x == 0) s_last = 0u;
+    if constexpr (L > 1) clear_bits<TS, L, FM>(S);   // then kept clear by compact_cover
     __syncthreads();
-    if (last) atomicMax(&s_last, last);
+    if (last && c.sub == 0) atomicMax(&s_last, last);
     if (rebuild_t) {
         // T_k by the forward's own recurrence (same operations, same order).
-        float T = 1.0f;
-        bool done = !c.inside;
+        FwdAcc<FM> a;
+        fwd_init(a, !c.inside);
         EntryRegs<FM> e;
         fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
         for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
-            clear_bits<TS, FM>(S);
-            __syncthreads();
-            store_entry<TS, FM, false>(S, c, e);
+            if constexpr (L == 1) {
+                clear_bits<TS, L, FM>(S);
+                __syncthreads();
+            }
+            store_entry<TS, L, FM, false>(S, c, e);
             __syncthreads();
             fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
-            if (!done) {
-                const int lim = (int)(r.y - c0);
-#pragma unroll
-                for (int wd = 0; wd < NW; ++wd) {
-                    uint32_t m = cover_word<TS, FM>(S, wd, lim);
-                    while (m != 0u && !done) {
-                        const int j = wd * 32 + (__ffs(m) - 1);
-                        m &= m - 1u;
-                        const int corner = corner_of(S.hit[j], c.lx, c.ly);
-                        float wx, wy, alpha, om;
-                        corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
-                        splat_alpha(S.opa[j], wx, wy, alpha, om);
-                        t_id[4u * S.vp[j] + (uint32_t)corner] = T;
-                        T = T * om;
-                        if (T < tau) done = true;
-                    }
-                }
+            const int lim = (int)(r.y - c0);
+            int n = 0;
+            if constexpr (L > 1) {
+                n = compact_cover<TS, L, FM>(S, c, lim);
+                __syncthreads();
             }
-            if (__syncthreads_and(done ? 1 : 0)) break;
+            if (!a.done) blend_chunk<TS, L, FM, false>(S, c, c0, lim, n, tau, a, t_id, nullptr);
+            if (__syncthreads_and(a.done ? 1 : 0)) break;
         }
         // the T_k written above are read back through the chunk loads below
         __threadfence_block();
@@ -300,56 +433,114 @@ __global__ __launch_bounds__(TS * TS) void k_tile_bwd(
     for (int k = (int)n_chunks - 1; k >= 0; --k) {
         const uint32_t c0 = r.x + (uint32_t)k * NT;
         __syncthreads();   // the previous chunk's LDS reads are done
-        clear_bits<TS, FM>(S);
-        __syncthreads();
-        store_entry<TS, FM, true>(S, c, e);
+        if constexpr (L == 1) {
+            clear_bits<TS, L, FM>(S);
+            __syncthreads();
+        }
+        store_entry<TS, L, FM, true>(S, c, e);
         __syncthreads();
         if (k > 0)
             fetch_entry<FT, FM, DYN, true>(e, c0 - NT, r.y, vals, payload, ps, Fd, t_id);
-        if (last > c0) {
-            const int lim = (int)(last - c0);
+        const int lim = last > c0 ? (int)(last - c0) : 0;
+        if constexpr (L == 1) {
+            if (lim > 0) {
 #pragma unroll
-            for (int wd = NW - 1; wd >= 0; --wd) {
-                uint32_t m = cover_word<TS, FM>(S, wd, lim);
-                while (m != 0u) {
-                    const int b = 31 - __clz(m);
-                    m &= ~(1u << b);
-                    const int j = wd * 32 + b;
+                for (int wd = NW - 1; wd >= 0; --wd) {
+                    uint32_t m = cover_word<TS, L, FM>(S, c, wd, lim);
+                    while (m != 0u) {
+                        const int b = 31 - __clz(m);
+                        m &= ~(1u << b);
+                        const int j = wd * 32 + b;
+                        const int corner = corner_of(S.hit[j], c.lx, c.ly);
+                        float wx, wy;
+                        corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
+                        const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
+                        const double alpha = (double)S.opa[j] * ((double)wx * (double)wy);
+                        double gc = 0.0;
+#pragma unroll
+                        for (int f = 0; f < FM; ++f)
+                            gc = __builtin_fma((double)g[f], (double)S.feat[j * FS + f], gc);
+                        const float4 t4 = S.tk[j];
+                        const double Tk =
+                            (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
+                        frec[id] = make_float2((float)(Tk * (gc - Y)), (float)(Tk * alpha));
+                        Y = __builtin_fma(1.0 - alpha, Y, alpha * gc);
+                    }
+                }
+            }
+        } else {
+            const int n = compact_cover<TS, L, FM>(S, c, lim);
+            __syncthreads();
+            const unsigned char* lst = S.lst + c.pix * TileChunk<TS, L, FM>::LS;
+            // groups of L slots from the end of the pixel's list, lanes in list order
+            for (int base = n > 0 ? ((n - 1) / L) * L : -1; base >= 0; base -= L) {
+                const int kk = base + c.sub;
+                const bool valid = kk < n;
+                double A = 0.0, B = 1.0, alpha = 0.0, gc = 0.0, Tk = 0.0;
+                uint32_t id = 0;
+                if (valid) {
+                    const int j = (int)lst[kk];
                     const int corner = corner_of(S.hit[j], c.lx, c.ly);
                     float wx, wy;
                     corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
-                    const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
-                    const double alpha = (double)S.opa[j] * ((double)wx * (double)wy);
-                    double gc = 0.0;
+                    id = 4u * S.vp[j] + (uint32_t)corner;
+                    alpha = (double)S.opa[j] * ((double)wx * (double)wy);
 #pragma unroll
                     for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)S.feat[j * FS + f], gc);
                     const float4 t4 = S.tk[j];
-                    const double Tk = (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
-                    frec[id] = make_float2((float)(Tk * (gc - Y)), (float)(Tk * alpha));
-                    Y = __builtin_fma(1.0 - alpha, Y, alpha * gc);
+                    Tk = (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
+                    A = alpha * gc;
+                    B = 1.0 - alpha;
                 }
+                // inclusive suffix composition of the maps Y -> A + B Y of lanes sub .. L-1
+#pragma unroll
+                for (int d = 1; d < L; d <<= 1) {
+                    const double A2 = __shfl_down(A, d, L);
+                    const double B2 = __shfl_down(B, d, L);
+                    if (c.sub + d < L) {
+                        A = __builtin_fma(B, A2, A);
+                        B = B * B2;
+                    }
+                }
+                double Ae = __shfl_down(A, 1, L), Be = __shfl_down(B, 1, L);
+                if (c.sub == L - 1) {
+                    Ae = 0.0;
+                    Be = 1.0;
+                }
+                const double y_next = __builtin_fma(Be, Y, Ae);
+                if (valid) frec[id] = make_float2((float)(Tk * (gc - y_next)), (float)(Tk * alpha));
+                Y = __builtin_fma(__shfl(B, 0, L), Y, __shfl(A, 0, L));
             }
         }
     }
 }
 
-template <typename FT, int FM, bool DYN, int TS>
+template <typename FT, int FM, bool DYN, int TS, int L>
 static void tile_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, float* image, float* t_final,
                        PixelState* state, float* t_id, float* splat_weight, hipStream_t s) {
-    hipLaunchKernelGGL((k_tile_fwd<FT, FM, DYN, TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, s, views, n_views,
-                       range, vals, payload, ps, Fd, tau, image, t_final, state, t_id,
-                       splat_weight);
+    hipLaunchKernelGGL((k_tile_fwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
+                       n_views, range, vals, payload, ps, Fd, tau, image, t_final, state, t_id, splat_weight);
 }
 
-template <typename FT, int FM, bool DYN, int TS>
+template <typename FT, int FM, bool DYN, int TS, int L>
 static void tile_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, const PixelState* state,
                        const float* g_img, const float* g_t, float* t_id, int rebuild_t, float2* frec,
                        hipStream_t s) {
-    hipLaunchKernelGGL((k_tile_bwd<FT, FM, DYN, TS>), dim3((unsigned)n_tiles), dim3(TS * TS), 0, s, views, n_views,
-                       range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_id,
-                       rebuild_t, frec);
+    hipLaunchKernelGGL((k_tile_bwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
+                       n_views, range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_id, rebuild_t, frec);
+}
+
+// Calls body.template operator()<TS, L>() for the tile shape.
+template <typename Body>
+static void dispatch_tile(int shape, Body&& body) {
+    switch (shape) {
+        case kTileShape16: body.template operator()<16, 1>(); break;
+        case kTileShape8x4: body.template operator()<8, 4>(); break;
+        case kTileShape8x2: body.template operator()<8, 2>(); break;
+        default: body.template operator()<8, 1>(); break;
+    }
 }
 
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
@@ -357,18 +548,16 @@ void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int
                      float tau, float* image, float* t_final, PixelState* state, float* t_id,
                      float* splat_weight, hipStream_t s) {
     if (n_tiles == 0) return;
-    auto go = [&]<int TS>() {
+    dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_fwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
-                                                        image, t_final, state, t_id, splat_weight, s);
+                tile_fwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
+                                                           image, t_final, state, t_id, splat_weight, s);
             else
-                tile_fwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, image,
-                                               t_final, state, t_id, splat_weight, s);
+                tile_fwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, image,
+                                                  t_final, state, t_id, splat_weight, s);
         });
-    };
-    if (tile_size_of(shape) == 16) go.template operator()<16>();
-    else go.template operator()<8>();
+    });
 }
 
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
@@ -376,18 +565,16 @@ void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
                      float* t_id, int rebuild_t, float2* frec, hipStream_t s) {
     if (n_tiles == 0) return;
-    auto go = [&]<int TS>() {
+    dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_bwd_t<__hip_bfloat16, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
-                                                        state, g_img, g_t, t_id, rebuild_t, frec, s);
+                tile_bwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
+                                                           state, g_img, g_t, t_id, rebuild_t, frec, s);
             else
-                tile_bwd_t<float, FM, DYN, TS>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, state,
-                                               g_img, g_t, t_id, rebuild_t, frec, s);
+                tile_bwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, state,
+                                                  g_img, g_t, t_id, rebuild_t, frec, s);
         });
-    };
-    if (tile_size_of(shape) == 16) go.template operator()<16>();
-    else go.template operator()<8>();
+    });
 }
 
 }  // namespace inpc

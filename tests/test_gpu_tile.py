@@ -1,8 +1,9 @@
-"""GPU parity of the tile-list blend (entries per 16x16 tile, one thread per
-pixel, chunks staged in LDS) against the FP64 oracle: the splat lists
-rebuilt from the device's sorted tile entries are bit-exact, images and
+"""GPU parity of the tile-list blend (entries per 8x8 or 16x16 tile, 1, 2 or
+4 lanes per pixel, chunks staged in LDS) against the FP64 oracle: the splat
+lists rebuilt from the device's sorted tile entries are bit-exact, images and
 gradients meet the same tolerances as the per-pixel-list path, RECOMPUTE
-equals SAVE bit for bit, and batched views and bfloat16 features work."""
+equals SAVE bit for bit, one lane per pixel equals the one-lane list blend
+bit for bit, and batched views and bfloat16 features work."""
 
 import numpy as np
 import pytest
@@ -17,24 +18,38 @@ from tests.test_gpu_parity import _scene_case
 pytestmark = pytest.mark.gpu
 
 
+# tile tunings under test, by a distinctive part of their table name
+VARIANTS = ["4096-key tiles, tile-list blend 8x8 (entries", "tile-list blend 16x16", "8x8, 4 lanes/pixel",
+            "8x8, 2 lanes/pixel", "fwd 4 lanes/pixel, bwd 1"]
+ONE_LANE = VARIANTS[:2]
+
+
 def tile_tunings():
     return [i for i, n in enumerate(pr.tuning_table()) if "tile-list" in n]
 
 
+def tuning_named(part):
+    hits = [i for i, n in enumerate(pr.tuning_table()) if part in n]
+    assert len(hits) == 1, (part, hits)
+    return hits[0]
+
+
 def test_tile_tunings_exist():
-    assert len(tile_tunings()) >= 1
+    assert len(tile_tunings()) >= len(VARIANTS)
+    for v in VARIANTS:
+        assert "tile-list" in pr.tuning_table()[tuning_named(v)]
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_config2_fwd_bwd_fd(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     s = workloads.config2(n=400_000)
     _scene_case(s.xyz, s.feat, s.opa, s.cam, tuning_id=tid, fd=32)
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_ragged_sizes_and_feature_widths(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     for (W, Hh, F) in [(1, 1, 4), (17, 33, 3), (300, 7, 16), (129, 65, 64), (97, 61, 20)]:
         rng = np.random.default_rng(W * 7 + Hh)
         cam = workloads.canonical_camera(W, Hh)
@@ -45,9 +60,9 @@ def test_tile_ragged_sizes_and_feature_widths(which):
         _scene_case(xyz, feat, opa, cam, tuning_id=tid, seed=W)
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_tau_zero_opaque_and_gt(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     rng = np.random.default_rng(5)
     cam = workloads.canonical_camera(48, 40)
     n = 8000
@@ -58,16 +73,16 @@ def test_tile_tau_zero_opaque_and_gt(which):
     _scene_case(xyz, feat, opa, cam, tau=0.0, tuning_id=tid, g_t=True, fd=16)
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_bf16(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     s = workloads.config2(n=200_000)
     _scene_case(s.xyz, s.feat, s.opa, s.cam, bf16=True, tuning_id=tid)
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_recompute_equals_save(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     s = workloads.config2(n=300_000)
     rng = np.random.default_rng(1)
     g = rng.normal(size=(s.cam.height * s.cam.width, s.F)).astype(np.float32)
@@ -80,21 +95,29 @@ def test_tile_recompute_equals_save(which):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("which", [0, 1])
-def test_tile_matches_list_path_closely(which):
+@pytest.mark.parametrize("which", ONE_LANE)
+@pytest.mark.parametrize("mode", ["save", "recompute"])
+def test_tile_matches_list_path_closely(which, mode):
     """Same fragments, same per-pixel float32 recurrence as the 1-lane list
-    blend: images agree bit for bit with tuning '1 lane/pixel'."""
-    one = [i for i, n in enumerate(pr.tuning_table()) if "1 lane/pixel" in n][0]
-    tid = tile_tunings()[which]
+    blend: images agree bit for bit with tuning '1 lane/pixel', and so do the
+    gradients (the backward's per-splat float64 chain is the same, and the
+    points combined inside the tile backward use the per-point reduction's
+    operations in its order)."""
+    one = [i for i, n in enumerate(pr.tuning_table()) if "1 lane/pixel 8x8" in n][0]
+    tid = tuning_named(which)
     s = workloads.config2(n=300_000)
-    a = H.gpu_forward(s.xyz, s.feat, s.opa, s.cam, tuning_id=one)
-    b = H.gpu_forward(s.xyz, s.feat, s.opa, s.cam, tuning_id=tid)
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(s.cam.height * s.cam.width, s.F)).astype(np.float32)
+    a = H.gpu_forward(s.xyz, s.feat, s.opa, s.cam, tuning_id=one, mode=mode)
+    b = H.gpu_forward(s.xyz, s.feat, s.opa, s.cam, tuning_id=tid, mode=mode)
     assert torch.equal(a["image"], b["image"]) and torch.equal(a["t_final"], b["t_final"])
+    ga, gb = H.gpu_backward(a, g), H.gpu_backward(b, g)
+    assert np.array_equal(ga[0], gb[0]) and np.array_equal(ga[1], gb[1])
 
 
-@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_batched_views_graph(which):
-    tid = tile_tunings()[which]
+    tid = tuning_named(which)
     b = workloads.config4(n_views=4, n_min=1e5, n_max=4e5)
     views = pr.make_views(b.cams, b.point_offset, b.point_count)
     g = np.concatenate([gi.reshape(-1, b.F) for gi in b.g_imgs])
