@@ -11,6 +11,10 @@ steps around the rasterizer (octree sampling, the appearance step, the
 per-point blend weight, multisampled inference, the probability update).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batched] [--no-cpu] [--no-next]
+
+Profile summaries (the text files under profiles/, from rocprofv3 output):
+  python bench.py --summarize-stats KERNEL_STATS_CSV TITLE COMMAND
+  python bench.py --summarize-counters FETCH_COUNTER_CSV WRITE_COUNTER_CSV
 """
 
 import argparse
@@ -29,6 +33,80 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# kernel name (without template arguments) -> bench stage
+KERNEL_STAGE = {
+    "k_project": "project", "k_emit_count": "emit", "k_emit_write": "emit", "k_tile_emit_write": "emit",
+    "k_scan_chunks": "emit", "k_radix_upsweep": "sort_upsweep", "k_scan_rows": "sort_scan",
+    "k_radix_downsweep": "sort_downsweep", "k_ranges": "ranges", "k_blend_fwd": "blend_fwd",
+    "k_tile_fwd": "blend_fwd", "k_blend_bwd": "blend_bwd", "k_tile_bwd": "blend_bwd",
+    "k_point_reduce": "point_reduce",
+}
+
+
+def summarize_stats(path, title, cmd):
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv)."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp):", "", "```", cmd, "```", "",
+           "| kernel | calls | avg us | total us | % |", "|---|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].split("(")[0].replace("void ", "")
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+COUNTER_CMDS = [
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o c3 --output-format csv -- "
+    "python3 bench.py --steps 2 --warmup 1 --no-batched --no-cpu --no-next --calib-copy",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o c3 --output-format csv -- "
+    "python3 bench.py --steps 2 --warmup 1 --no-batched --no-cpu --no-next --calib-copy",
+]
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """HBM bytes per launch of every rasterizer kernel from two rocprofv3
+    counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
+    what the counter reads for the 1 GiB device copy of the same run.
+    Returns (markdown summary, json record keyed by bench stage)."""
+    import collections
+    import csv
+
+    def load(p):
+        d = collections.defaultdict(list)
+        for r in csv.DictReader(open(p)):
+            d[r["Kernel_Name"].split("(")[0].replace("void ", "")].append(float(r["Counter_Value"]))
+        return d
+
+    fk, wk = load(fetch_csv), load(write_csv)
+    cal_f, cal_w = max(fk["__amd_rocclr_copyBuffer"]), max(wk["__amd_rocclr_copyBuffer"])
+    gib_kib = 1024.0 * 1024.0
+    fs, ws = gib_kib / cal_f, gib_kib / cal_w
+    rec = {"workload": "8M points, 1920x1080, F=16 float32, forward+backward", "fetch_scale": fs,
+           "write_scale": ws, "calibration": "1 GiB device-to-device copy in the same runs: "
+           f"FETCH_SIZE reads {cal_f:.0f} KB, WRITE_SIZE {cal_w:.0f} KB",
+           "commands": COUNTER_CMDS, "source_sha256": source_digest(), "per_launch_bytes": {}}
+    lines = ["# HBM traffic per kernel launch: 8M points, 1920x1080, F=16 float32, forward+backward", "",
+             "Counters from two runs (run from /tmp with TMPDIR=/tmp), summarized with "
+             "`python bench.py --summarize-counters <fetch csv> <write csv>`:", "", "```"] + COUNTER_CMDS + [
+             "```", "", f"Calibration: a 1 GiB device copy in the same runs reads FETCH_SIZE = {cal_f:.0f} KB "
+             f"and WRITE_SIZE = {cal_w:.0f} KB, so fetch counts are scaled by {fs:.3f} and write counts by "
+             f"{ws:.3f}.", "", "| kernel | launches | fetch GB/launch | write GB/launch | total GB/launch |",
+             "|---|---:|---:|---:|---:|"]
+    per_stage = collections.defaultdict(float)
+    for k in sorted(fk, key=lambda k: -sum(fk[k]) / len(fk[k])):
+        short = k.split("<")[0].replace("inpc::", "")
+        if short not in KERNEL_STAGE:
+            continue
+        f = sum(fk[k]) / len(fk[k]) * fs * 1024
+        w = sum(wk[k]) / len(wk[k]) * ws * 1024 if k in wk else 0.0
+        lines.append(f"| `{k}` | {len(fk[k])} | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")
+        per_stage[KERNEL_STAGE[short]] += f + w
+    # stages whose kernels run once per step (the sorts run several passes of different widths)
+    rec["per_launch_bytes"] = {k: v for k, v in per_stage.items() if not k.startswith("sort_")}
+    return "\n".join(lines) + "\n", rec
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +119,10 @@ def parse():
     ap.add_argument("--tuning", type=int, default=-1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("CSV", "TITLE", "COMMAND"),
+                    help="print the markdown summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/counters_config3.md and profiles/traffic_config3.json and exit")
     return ap.parse_args()
 
 
@@ -103,6 +185,15 @@ def measured_traffic(stage: str, launches: float):
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        print(summarize_stats(*args.summarize_stats), end="")
+        return
+    if args.summarize_counters:
+        md, rec = summarize_counters(*args.summarize_counters)
+        open(os.path.join(ROOT, "profiles", "counters_config3.md"), "w").write(md)
+        json.dump(rec, open(os.path.join(ROOT, "profiles", "traffic_config3.json"), "w"), indent=1)
+        print(md, end="")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this rasterizer runs on one GPU; multi-GPU runs are not supported "
               "(use --gpus 1)", file=sys.stderr)

@@ -195,7 +195,7 @@ struct Carver {
 // splat ids and per-pixel ranges; it lives in ``saved`` in SAVE mode and in
 // the workspace of whichever pass builds it in RECOMPUTE mode.
 struct FragOffsets {
-    size_t rec, ids, range, tk;   // tk: T_k of every blended splat (by sorted slot, or by splat id)
+    size_t rec, ids, range, tk;   // tk: T_k of every blended splat (by sorted slot; tile lists: four per entry)
     size_t payload;               // record + feature row per view point (tile lists)
 };
 struct BuildOffsets {  // transient buffers of the fragment build
@@ -227,7 +227,7 @@ static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
     f.rec = c.take((size_t)pb.n_vp * sizeof(PointRec));
     f.ids = c.take((size_t)4 * pb.n_vp * 4);
     f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
-    f.tk = c.take((size_t)4 * pb.n_vp * 4);
+    f.tk = c.take((size_t)4 * pb.n_vp * 16);   // at most 4 entries per point, 4 floats each
     f.payload = c.take((size_t)pb.n_vp * payload_stride(pb.F, pb.fdt));
 }
 
@@ -447,7 +447,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
                             (int)pb.views.size(), pb.n_tiles,
                             at<uint2>(frag_base, fo.range), at<uint32_t>(frag_base, fo.ids),
                             at<unsigned char>(frag_base, fo.payload), payload_stride(pb.F, pb.fdt), tau, image, t_final,
-                            at<PixelState>(saved, L.s_state), tk, splat_weight, s);
+                            at<PixelState>(saved, L.s_state), reinterpret_cast<float4*>(tk), splat_weight, s);
         else
             launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
                              (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
@@ -502,7 +502,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
                         at<const unsigned char>(const_cast<void*>(frag_base), fo->payload),
                         payload_stride(pb.F, pb.fdt), tau,
                         at<const PixelState>(sv, L.s_state), g_img, g_t,
-                        at<float>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
+                        at<float4>(const_cast<void*>(frag_base), fo->tk), pb.mode == INPC_RECOMPUTE ? 1 : 0,
                         frec, s);
     else
         launch_blend_bwd(pb.F, pb.fdt, bshape, views, (int)pb.views.size(), pb.n_tiles,

@@ -139,15 +139,17 @@ void launch_appearance_bwd(const float* xyz, const float* raw, const GpuView* vi
 // Per-pixel average of K planes of ``plane`` floats each (float64 sums).
 void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipStream_t s);
 
-// Tile-list blend forward / backward (one block per tile; T_k by splat id).
+// Tile-list blend forward / backward (one block per tile).  t_ent holds, per
+// sorted tile entry, T_k of the entry's four splats (by corner; zero where
+// the splat is not blended in that tile).
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
                      const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
-                     float tau, float* image, float* t_final, PixelState* state, float* t_id,
+                     float tau, float* image, float* t_final, PixelState* state, float4* t_ent,
                      float* splat_weight, hipStream_t s);
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
                      const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
-                     float* t_id, int rebuild_t, float2* frec, hipStream_t s);
+                     float4* t_ent, int rebuild_t, float2* frec, hipStream_t s);
 
 // Per-point blend weight from the per-splat weights T alpha (indexed by splat id).
 void launch_blend_weight(int64_t n_vp, const PointRec* rec, const float* splat_weight, float* out,

@@ -121,7 +121,7 @@ template <typename FT, int FM, bool DYN, bool WANT_T>
 __device__ __forceinline__ void fetch_entry(EntryRegs<FM>& e, uint32_t c0, uint32_t end,
                                             const uint32_t* __restrict__ vals,
                                             const unsigned char* __restrict__ payload, int ps, int Fd,
-                                            const float* __restrict__ t_id) {
+                                            const float4* __restrict__ t_ent) {
     const uint32_t j = c0 + threadIdx.x;
     e.valid = c0 < end && j < end;
     if (e.valid) {
@@ -129,7 +129,7 @@ __device__ __forceinline__ void fetch_entry(EntryRegs<FM>& e, uint32_t c0, uint3
         const unsigned char* row = payload + (size_t)e.vp * ps;
         e.r = *reinterpret_cast<const PointRec*>(row);
         payload_feat<FT, FM, DYN>(reinterpret_cast<const FT*>(row + sizeof(PointRec)), Fd, e.cf);
-        if constexpr (WANT_T) e.t4 = reinterpret_cast<const float4*>(t_id)[e.vp];
+        if constexpr (WANT_T) e.t4 = t_ent[j];
     }
 }
 
@@ -251,10 +251,11 @@ __device__ __forceinline__ void fwd_init(FwdAcc<FM>& a, bool done) {
 // L == 1: walks the pixel's bits (the one-lane float32 recurrence, operation
 // for operation); L > 1: takes the n slots listed by compact_cover L at a
 // time with the grouped transmittance step.  COLOUR: accumulate the colour
-// and write the per-splat weights T_k alpha_k; T_k goes to t_id if given.
+// and write the per-splat weights T_k alpha_k.  s_tk (LDS, four floats per
+// chunk entry, by corner) receives T_k if given.
 template <int TS, int L, int FM, bool COLOUR>
 __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const TileCtx& c, uint32_t c0, int lim,
-                                            int n, float tau, FwdAcc<FM>& a, float* __restrict__ t_id,
+                                            int n, float tau, FwdAcc<FM>& a, float* s_tk,
                                             float* __restrict__ splat_weight) {
     constexpr int FS = TileChunk<TS, L, FM>::FS, NW = TileDims<TS, L>::NW;
     if constexpr (L == 1) {
@@ -275,7 +276,7 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
                     for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
                     if (splat_weight) splat_weight[id] = ta;
                 }
-                if (t_id) t_id[id] = a.T;
+                if (s_tk) s_tk[4 * j + corner] = a.T;
                 a.T = a.T * om;
                 ++a.nb;
                 a.last = c0 + (uint32_t)j + 1u;
@@ -306,7 +307,7 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
                     for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
                     if (splat_weight) splat_weight[id] = ta;
                 }
-                if (t_id) t_id[id] = g.tb;
+                if (s_tk) s_tk[4 * j + corner] = g.tb;
             }
             // the blended lanes are a prefix of the group, in list order
             const int gbase = __lane_id() - c.sub;
@@ -326,9 +327,10 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, float* __restrict__ image, float* __restrict__ t_final, PixelState* __restrict__ state,
-    float* __restrict__ t_id, float* __restrict__ splat_weight) {
+    float4* __restrict__ t_ent, float* __restrict__ splat_weight) {
     constexpr int NT = TileDims<TS, L>::NT;
     __shared__ TileChunk<TS, L, FM> S;
+    float* s_tk = t_ent ? reinterpret_cast<float*>(S.tk) : nullptr;
     const TileCtx c = tile_ctx<TS, L>(views, n_views);
     const uint2 r = range[c.tile];
     FwdAcc<FM> a;
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
             __syncthreads();
         }
         store_entry<TS, L, FM, false>(S, c, e);
+        if (s_tk) S.tk[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         __syncthreads();
         fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
         const int lim = (int)(r.y - c0);
@@ -354,8 +357,11 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
             n = compact_cover<TS, L, FM>(S, c, lim);
             __syncthreads();
         }
-        if (!a.done) blend_chunk<TS, L, FM, true>(S, c, c0, lim, n, tau, a, t_id, splat_weight);
-        if (__syncthreads_and(a.done ? 1 : 0)) break;
+        if (!a.done) blend_chunk<TS, L, FM, true>(S, c, c0, lim, n, tau, a, s_tk, splat_weight);
+        const bool all_done = __syncthreads_and(a.done ? 1 : 0);
+        // the T_k of the chunk's entries, by entry (coalesced)
+        if (s_tk && c0 + threadIdx.x < r.y) t_ent[c0 + threadIdx.x] = S.tk[threadIdx.x];
+        if (all_done) break;
     }
 #pragma unroll
     for (int mm = L / 2; mm >= 1; mm >>= 1) {
@@ -378,7 +384,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
     const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, const PixelState* __restrict__ state, const float* __restrict__ g_img,
-    const float* __restrict__ g_t, float* __restrict__ t_id, int rebuild_t, float2* __restrict__ frec) {
+    const float* __restrict__ g_t, float4* __restrict__ t_ent, int rebuild_t, float2* __restrict__ frec) {
     constexpr int FS = TileChunk<TS, L, FM>::FS, NT = TileDims<TS, L>::NT, NW = TileDims<TS, L>::NW;
     __shared__ TileChunk<TS, L, FM> S;
     __shared__ uint32_t s_last;
@@ -401,6 +407,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                 __syncthreads();
             }
             store_entry<TS, L, FM, false>(S, c, e);
+            S.tk[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             __syncthreads();
             fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
             const int lim = (int)(r.y - c0);
@@ -409,8 +416,11 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                 n = compact_cover<TS, L, FM>(S, c, lim);
                 __syncthreads();
             }
-            if (!a.done) blend_chunk<TS, L, FM, false>(S, c, c0, lim, n, tau, a, t_id, nullptr);
-            if (__syncthreads_and(a.done ? 1 : 0)) break;
+            if (!a.done)
+                blend_chunk<TS, L, FM, false>(S, c, c0, lim, n, tau, a, reinterpret_cast<float*>(S.tk), nullptr);
+            const bool all_done = __syncthreads_and(a.done ? 1 : 0);
+            if (c0 + threadIdx.x < r.y) t_ent[c0 + threadIdx.x] = S.tk[threadIdx.x];
+            if (all_done) break;
         }
         // the T_k written above are read back through the chunk loads below
         __threadfence_block();
@@ -429,7 +439,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
     }
     const uint32_t n_chunks = (lmax - r.x + NT - 1) / NT;
     EntryRegs<FM> e;
-    fetch_entry<FT, FM, DYN, true>(e, r.x + (n_chunks - 1) * NT, r.y, vals, payload, ps, Fd, t_id);
+    fetch_entry<FT, FM, DYN, true>(e, r.x + (n_chunks - 1) * NT, r.y, vals, payload, ps, Fd, t_ent);
     for (int k = (int)n_chunks - 1; k >= 0; --k) {
         const uint32_t c0 = r.x + (uint32_t)k * NT;
         __syncthreads();   // the previous chunk's LDS reads are done
@@ -440,7 +450,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
         store_entry<TS, L, FM, true>(S, c, e);
         __syncthreads();
         if (k > 0)
-            fetch_entry<FT, FM, DYN, true>(e, c0 - NT, r.y, vals, payload, ps, Fd, t_id);
+            fetch_entry<FT, FM, DYN, true>(e, c0 - NT, r.y, vals, payload, ps, Fd, t_ent);
         const int lim = last > c0 ? (int)(last - c0) : 0;
         if constexpr (L == 1) {
             if (lim > 0) {
@@ -518,18 +528,18 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
 template <typename FT, int FM, bool DYN, int TS, int L>
 static void tile_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, float* image, float* t_final,
-                       PixelState* state, float* t_id, float* splat_weight, hipStream_t s) {
+                       PixelState* state, float4* t_ent, float* splat_weight, hipStream_t s) {
     hipLaunchKernelGGL((k_tile_fwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
-                       n_views, range, vals, payload, ps, Fd, tau, image, t_final, state, t_id, splat_weight);
+                       n_views, range, vals, payload, ps, Fd, tau, image, t_final, state, t_ent, splat_weight);
 }
 
 template <typename FT, int FM, bool DYN, int TS, int L>
 static void tile_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, const PixelState* state,
-                       const float* g_img, const float* g_t, float* t_id, int rebuild_t, float2* frec,
+                       const float* g_img, const float* g_t, float4* t_ent, int rebuild_t, float2* frec,
                        hipStream_t s) {
     hipLaunchKernelGGL((k_tile_bwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
-                       n_views, range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_id, rebuild_t, frec);
+                       n_views, range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_ent, rebuild_t, frec);
 }
 
 // Calls body.template operator()<TS, L>() for the tile shape.
@@ -545,17 +555,17 @@ static void dispatch_tile(int shape, Body&& body) {
 
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
                      const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
-                     float tau, float* image, float* t_final, PixelState* state, float* t_id,
+                     float tau, float* image, float* t_final, PixelState* state, float4* t_ent,
                      float* splat_weight, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
                 tile_fwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
-                                                           image, t_final, state, t_id, splat_weight, s);
+                                                           image, t_final, state, t_ent, splat_weight, s);
             else
                 tile_fwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, image,
-                                                  t_final, state, t_id, splat_weight, s);
+                                                  t_final, state, t_ent, splat_weight, s);
         });
     });
 }
@@ -563,16 +573,16 @@ void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
                      const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
-                     float* t_id, int rebuild_t, float2* frec, hipStream_t s) {
+                     float4* t_ent, int rebuild_t, float2* frec, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
                 tile_bwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
-                                                           state, g_img, g_t, t_id, rebuild_t, frec, s);
+                                                           state, g_img, g_t, t_ent, rebuild_t, frec, s);
             else
                 tile_bwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, state,
-                                                  g_img, g_t, t_id, rebuild_t, frec, s);
+                                                  g_img, g_t, t_ent, rebuild_t, frec, s);
         });
     });
 }
