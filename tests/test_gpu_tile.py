@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 # tile tunings under test, by a distinctive part of their table name
 VARIANTS = ["4096-key tiles, tile-list blend 8x8 (entries", "tile-list blend 16x16", "8x8, 4 lanes/pixel",
-            "8x8, 2 lanes/pixel", "fwd 4 lanes/pixel, bwd 1"]
+            "8x8, 2 lanes/pixel", "fwd 4 lanes/pixel, bwd 1", "fwd 1 lane/pixel, bwd 2"]
 ONE_LANE = VARIANTS[:2]
 
 
