@@ -198,9 +198,11 @@ struct Carver {
 struct FragOffsets {
     size_t rec, ids, range, tk;   // tk: T_k of every blended splat (by sorted slot; tile lists: four per entry)
     size_t payload;               // record + feature row per view point (tile lists)
+    size_t perm;                  // tile dispatch order, heaviest first (tile lists)
 };
 struct BuildOffsets {  // transient buffers of the fragment build
     size_t views, scalars, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b, chunks, pk_a, pk_b, pv_other, counts;
+    size_t order;   // tile-order class counters
 };
 struct Layout {
     size_t saved_bytes, fwd_bytes, bwd_bytes;
@@ -230,6 +232,7 @@ static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
     f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
     f.tk = c.take((size_t)4 * pb.n_vp * 16);   // at most 4 entries per point, 4 floats each
     f.payload = c.take((size_t)pb.n_vp * payload_stride(pb.F, pb.fdt));
+    f.perm = c.take((size_t)pb.n_pixels * 4);   // tiles <= pixels
 }
 
 static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
@@ -247,6 +250,7 @@ static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
     b.pk_b = c.take(mb * 4);
     b.pv_other = c.take(mb * 4);
     b.counts = c.take(max_counts_words(pb) * 4);
+    b.order = c.take(256);
 }
 
 static Layout make_layout(const Problem& pb) {
@@ -418,6 +422,9 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
         ProfScope p(kStRanges, s);
         launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, tile ? pb.n_tiles : pb.n_pixels,
                       at<uint2>(frag_base, fo.range), s);
+        if (tile)
+            launch_tile_order(at<uint2>(frag_base, fo.range), pb.n_tiles, at<uint32_t>(build_base, bo.order),
+                              at<uint32_t>(frag_base, fo.perm), s);
     }
 }
 
@@ -445,7 +452,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
         float* tk = pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr;
         if (is_tile_shape(tn.blend_shape))
             launch_tile_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
-                            (int)pb.views.size(), pb.n_tiles,
+                            (int)pb.views.size(), pb.n_tiles, at<uint32_t>(frag_base, fo.perm),
                             at<uint2>(frag_base, fo.range), at<uint32_t>(frag_base, fo.ids),
                             at<unsigned char>(frag_base, fo.payload), payload_stride(pb.F, pb.fdt), tau, image, t_final,
                             at<PixelState>(saved, L.s_state), reinterpret_cast<float4*>(tk), splat_weight, s);
@@ -498,6 +505,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     ProfScope p(kStBlendBwd, s);
     if (is_tile_shape(bshape))
         launch_tile_bwd(pb.F, pb.fdt, bshape, views, (int)pb.views.size(), pb.n_tiles,
+                        at<const uint32_t>(const_cast<void*>(frag_base), fo->perm),
                         at<const uint2>(const_cast<void*>(frag_base), fo->range),
                         at<const uint32_t>(const_cast<void*>(frag_base), fo->ids),
                         at<const unsigned char>(const_cast<void*>(frag_base), fo->payload),

@@ -95,6 +95,11 @@ bool sort_valid(int digit, int items);
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
                    int64_t n_pixels, uint2* range, hipStream_t s);
 
+// Tile dispatch order: perm[0, n_tiles) lists the tiles by descending entry
+// count class (bit length of the count), so the blends start the heaviest
+// tiles first.  cls_tmp: 33 words of scratch.
+void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* cls_tmp, uint32_t* perm, hipStream_t s);
+
 // Per-pixel state kept from the forward blend for the backward.
 struct alignas(16) PixelState {
     uint32_t n_blended;  // splats blended before termination
@@ -139,15 +144,16 @@ void launch_appearance_bwd(const float* xyz, const float* raw, const GpuView* vi
 // Per-pixel average of K planes of ``plane`` floats each (float64 sums).
 void launch_mean_planes(const float* in, int K, int64_t plane, float* out, hipStream_t s);
 
-// Tile-list blend forward / backward (one block per tile).  t_ent holds, per
+// Tile-list blend forward / backward (one block per tile, block b blending
+// tile perm[b]).  t_ent holds, per
 // sorted tile entry, T_k of the entry's four splats (by corner; zero where
 // the splat is not blended in that tile).
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
+                     const uint32_t* perm, const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, float* image, float* t_final, PixelState* state, float4* t_ent,
                      float* splat_weight, hipStream_t s);
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
+                     const uint32_t* perm, const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
                      float4* t_ent, int rebuild_t, float2* frec, hipStream_t s);
 

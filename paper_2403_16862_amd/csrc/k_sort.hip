@@ -297,4 +297,68 @@ void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m
                        pkey_sorted, m_dev, (uint32_t)m_bound, range);
 }
 
+// ------------------------------------------------------------ tile order
+// Blocks are dispatched in index order, so a heavy tile launched late
+// becomes the tail of a blend launch.  perm lists the tiles by descending
+// size class (class = bit length of the entry count), so the heaviest tiles
+// start first.  The order inside a class is arbitrary (atomics): every tile
+// is blended on its own, so results do not depend on it.
+constexpr int kOrderClasses = 33;
+
+__device__ __forceinline__ int size_class(const uint2 rg) {
+    const uint32_t n = rg.y - rg.x;
+    return n ? 32 - __clz(n) : 0;
+}
+
+__global__ __launch_bounds__(256) void k_order_hist(const uint2* __restrict__ range, int64_t n_tiles,
+                                                    uint32_t* __restrict__ cls_cnt) {
+    __shared__ uint32_t h[kOrderClasses];
+    for (int i = threadIdx.x; i < kOrderClasses; i += 256) h[i] = 0u;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n_tiles) atomicAdd(&h[size_class(range[t])], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOrderClasses; i += 256)
+        if (h[i]) atomicAdd(&cls_cnt[i], h[i]);
+}
+
+// cls_cnt -> start of each class in perm, largest class first.
+__global__ void k_order_scan(uint32_t* __restrict__ cls_cnt) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int c = kOrderClasses - 1; c >= 0; --c) {
+        const uint32_t n = cls_cnt[c];
+        cls_cnt[c] = run;
+        run += n;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_order_place(const uint2* __restrict__ range, int64_t n_tiles,
+                                                     uint32_t* __restrict__ cls_next, uint32_t* __restrict__ perm) {
+    __shared__ uint32_t h[kOrderClasses];
+    __shared__ uint32_t base[kOrderClasses];
+    for (int i = threadIdx.x; i < kOrderClasses; i += 256) h[i] = 0u;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int c = 0;
+    uint32_t local = 0;
+    if (t < n_tiles) {
+        c = size_class(range[t]);
+        local = atomicAdd(&h[c], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOrderClasses; i += 256) base[i] = h[i] ? atomicAdd(&cls_next[i], h[i]) : 0u;
+    __syncthreads();
+    if (t < n_tiles) perm[base[c] + local] = (uint32_t)t;
+}
+
+void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* cls_tmp, uint32_t* perm, hipStream_t s) {
+    if (n_tiles == 0) return;
+    const unsigned blocks = (unsigned)((n_tiles + 255) / 256);
+    launch_fill_u32(cls_tmp, 0u, kOrderClasses, s);
+    hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, s, range, n_tiles, cls_tmp);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, cls_tmp);
+    hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, s, range, n_tiles, cls_tmp, perm);
+}
+
 }  // namespace inpc

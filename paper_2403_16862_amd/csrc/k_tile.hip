@@ -44,9 +44,10 @@ struct TileCtx {
 };
 
 template <int TS, int L>
-__device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, int n_views) {
+__device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, int n_views,
+                                            const uint32_t* __restrict__ perm) {
     TileCtx c;
-    c.tile = xcd_remap(blockIdx.x, gridDim.x);
+    c.tile = perm[blockIdx.x];
     const int v = n_views == 1 ? 0
                                : find_view(views, n_views, (int64_t)c.tile,
                                            [](const GpuView& g) { return g.tile_offset; });
@@ -324,14 +325,14 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
 
 template <typename FT, int FM, bool DYN, int TS, int L>
 __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
-    const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
+    const GpuView* __restrict__ views, int n_views, const uint32_t* __restrict__ perm, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, float* __restrict__ image, float* __restrict__ t_final, PixelState* __restrict__ state,
     float4* __restrict__ t_ent, float* __restrict__ splat_weight) {
     constexpr int NT = TileDims<TS, L>::NT;
     __shared__ TileChunk<TS, L, FM> S;
     float* s_tk = t_ent ? reinterpret_cast<float*>(S.tk) : nullptr;
-    const TileCtx c = tile_ctx<TS, L>(views, n_views);
+    const TileCtx c = tile_ctx<TS, L>(views, n_views, perm);
     const uint2 r = range[c.tile];
     FwdAcc<FM> a;
     fwd_init(a, !c.inside);
@@ -381,14 +382,14 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
 
 template <typename FT, int FM, bool DYN, int TS, int L>
 __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
-    const GpuView* __restrict__ views, int n_views, const uint2* __restrict__ range,
+    const GpuView* __restrict__ views, int n_views, const uint32_t* __restrict__ perm, const uint2* __restrict__ range,
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, const PixelState* __restrict__ state, const float* __restrict__ g_img,
     const float* __restrict__ g_t, float4* __restrict__ t_ent, int rebuild_t, float2* __restrict__ frec) {
     constexpr int FS = TileChunk<TS, L, FM>::FS, NT = TileDims<TS, L>::NT, NW = TileDims<TS, L>::NW;
     __shared__ TileChunk<TS, L, FM> S;
     __shared__ uint32_t s_last;
-    const TileCtx c = tile_ctx<TS, L>(views, n_views);
+    const TileCtx c = tile_ctx<TS, L>(views, n_views, perm);
     const uint2 r = range[c.tile];
     const uint32_t last = c.inside ? state[c.q].pad0 : 0u;
     if (threadIdx.x == 0) s_last = 0u;
@@ -526,20 +527,22 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
 }
 
 template <typename FT, int FM, bool DYN, int TS, int L>
-static void tile_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
+static void tile_fwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint32_t* perm, const uint2* range,
+                       const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, float* image, float* t_final,
                        PixelState* state, float4* t_ent, float* splat_weight, hipStream_t s) {
     hipLaunchKernelGGL((k_tile_fwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
-                       n_views, range, vals, payload, ps, Fd, tau, image, t_final, state, t_ent, splat_weight);
+                       n_views, perm, range, vals, payload, ps, Fd, tau, image, t_final, state, t_ent, splat_weight);
 }
 
 template <typename FT, int FM, bool DYN, int TS, int L>
-static void tile_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint2* range, const uint32_t* vals,
+static void tile_bwd_t(const GpuView* views, int n_views, int64_t n_tiles, const uint32_t* perm, const uint2* range,
+                       const uint32_t* vals,
                        const unsigned char* payload, int ps, int Fd, float tau, const PixelState* state,
                        const float* g_img, const float* g_t, float4* t_ent, int rebuild_t, float2* frec,
                        hipStream_t s) {
     hipLaunchKernelGGL((k_tile_bwd<FT, FM, DYN, TS, L>), dim3((unsigned)n_tiles), dim3(TS * TS * L), 0, s, views,
-                       n_views, range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_ent, rebuild_t, frec);
+                       n_views, perm, range, vals, payload, ps, Fd, tau, state, g_img, g_t, t_ent, rebuild_t, frec);
 }
 
 // Calls body.template operator()<TS, L>() for the tile shape.
@@ -554,34 +557,34 @@ static void dispatch_tile(int shape, Body&& body) {
 }
 
 void launch_tile_fwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
+                     const uint32_t* perm, const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, float* image, float* t_final, PixelState* state, float4* t_ent,
                      float* splat_weight, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_fwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
+                tile_fwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, perm, range, vals, payload, ps, F, tau,
                                                            image, t_final, state, t_ent, splat_weight, s);
             else
-                tile_fwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, image,
+                tile_fwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, perm, range, vals, payload, ps, F, tau, image,
                                                   t_final, state, t_ent, splat_weight, s);
         });
     });
 }
 
 void launch_tile_bwd(int F, int feat_dtype, int shape, const GpuView* views, int n_views, int64_t n_tiles,
-                     const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
+                     const uint32_t* perm, const uint2* range, const uint32_t* vals, const unsigned char* payload, int ps,
                      float tau, const PixelState* state, const float* g_img, const float* g_t,
                      float4* t_ent, int rebuild_t, float2* frec, hipStream_t s) {
     if (n_tiles == 0) return;
     dispatch_tile(shape, [&]<int TS, int L>() {
         dispatch_f(F, [&]<int FM, bool DYN>() {
             if (feat_dtype == 1)
-                tile_bwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau,
+                tile_bwd_t<__hip_bfloat16, FM, DYN, TS, L>(views, n_views, n_tiles, perm, range, vals, payload, ps, F, tau,
                                                            state, g_img, g_t, t_ent, rebuild_t, frec, s);
             else
-                tile_bwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, range, vals, payload, ps, F, tau, state,
+                tile_bwd_t<float, FM, DYN, TS, L>(views, n_views, n_tiles, perm, range, vals, payload, ps, F, tau, state,
                                                   g_img, g_t, t_ent, rebuild_t, frec, s);
         });
     });
