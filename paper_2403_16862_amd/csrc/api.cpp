@@ -21,9 +21,9 @@ namespace inpc {
 // zdigit / pdigit = 0: choose the digit width from the key width (fewest
 // passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
+    {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
     {0, 0, 16, kTileShape8, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 1 lane/pixel, bwd 2"},
     {0, 0, 16, kTileShape8x2, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, 2 lanes/pixel"},
-    {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
     {0, 0, 32, kTileShape8, kTileShape8, "auto digits, 8192-key tiles, tile-list blend 8x8 (entries per tile)"},
     {0, 0, 16, kTileShape16, kTileShape16, "auto digits, 4096-key tiles, tile-list blend 16x16 (entries per tile)"},
     {0, 0, 16, kTileShape8x4, kTileShape8x4, "auto digits, 4096-key tiles, tile-list blend 8x8, 4 lanes/pixel"},
