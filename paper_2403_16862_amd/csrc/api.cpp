@@ -861,7 +861,7 @@ int inpc_appearance_bwd(const float* xyz, const float* raw, int64_t n_points, co
 
 // ------------------------------------------------------------ sampling
 struct SampleLayout {
-    size_t scalars, phat, cdf, tiles, counts, count_cdf, total;
+    size_t scalars, phat, cdf, tiles, counts, count_cdf, guide, total;
 };
 
 static SampleLayout sample_layout(int64_t n_leaves) {
@@ -874,6 +874,7 @@ static SampleLayout sample_layout(int64_t n_leaves) {
     l.tiles = c.take(8 * T);
     l.counts = c.take(4 * L);
     l.count_cdf = c.take(8 * L);
+    l.guide = c.take(4 * (((size_t)1 << guide_bits(n_leaves)) + 1));
     l.total = c.off;
     return l;
 }
@@ -955,7 +956,8 @@ int inpc_sample_view(const float* centre, const int32_t* level, const float* pro
     }
     {
         ProfScope p(kStSampleDraw, s);
-        launch_sample_view(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, sc, seed0, seed1,
+        launch_sample_view(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, at<uint32_t>(ws, l.guide), sc,
+                           seed0, seed1,
                            n_samples, max_rounds, xyz, leaf_index,
                            reinterpret_cast<unsigned long long*>(n_unresolved), s);
     }
@@ -984,7 +986,8 @@ int inpc_sample_global(const float* centre, const int32_t* level, const float* p
     }
     {
         ProfScope p(kStSampleDraw, s);
-        launch_sample_global(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, seed0, seed1,
+        launch_sample_global(centre, level, root_size, at<uint64_t>(ws, l.cdf), n_leaves, at<uint32_t>(ws, l.guide),
+                             seed0, seed1,
                              n_samples, at<uint32_t>(ws, l.counts), at<uint64_t>(ws, l.tiles),
                              at<uint64_t>(ws, l.count_cdf), xyz, leaf_index, s);
     }

@@ -123,13 +123,16 @@ struct LevelTable {
 void launch_sample_weights(const float* centre, const int32_t* level, const float* prob, int64_t n_leaves,
                            float root, float tau_d, const LevelTable& lt, const SampleCam& cam, bool view,
                            float* phat, uint32_t* max_bits, uint64_t* tile_sum, uint64_t* cdf, hipStream_t s);
+// guide: 2^guide_bits(n_leaves) + 1 words of scratch (the inverse-CDF search's guide table).
+int guide_bits(int64_t n_leaves);
 void launch_sample_view(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
-                        int64_t n_leaves, const SampleCam& cam, uint64_t seed0, uint64_t seed1, int64_t n,
-                        int max_rounds, float* xyz, int32_t* leaf, unsigned long long* unresolved,
+                        int64_t n_leaves, uint32_t* guide, const SampleCam& cam, uint64_t seed0, uint64_t seed1,
+                        int64_t n, int max_rounds, float* xyz, int32_t* leaf, unsigned long long* unresolved,
                         hipStream_t s);
 void launch_sample_global(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
-                          int64_t n_leaves, uint64_t seed0, uint64_t seed1, int64_t n, uint32_t* counts,
-                          uint64_t* tile_sum, uint64_t* count_cdf, float* xyz, int32_t* leaf, hipStream_t s);
+                          int64_t n_leaves, uint32_t* guide, uint64_t seed0, uint64_t seed1, int64_t n,
+                          uint32_t* counts, uint64_t* tile_sum, uint64_t* count_cdf, float* xyz, int32_t* leaf,
+                          hipStream_t s);
 void launch_prob_update(const int32_t* leaf, const float* b, int64_t n, int64_t n_leaves, float lambda_u,
                         float* prob, float* subdiv, uint32_t* kmax, uint32_t* kmin, hipStream_t s);
 

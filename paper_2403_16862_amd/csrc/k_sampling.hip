@@ -248,10 +248,40 @@ __device__ __forceinline__ int64_t upper_bound_u64(const uint64_t* __restrict__ 
     return lo;
 }
 
+// Guide table of the inverse-CDF search: bucket b of 2^g holds the leaf
+// upper_bound(cdf, T_b) with T_b = the draw target of the smallest 64-bit
+// word whose top g bits are b (T_G = total).  Targets are monotone in the
+// word, so the leaf of a word in bucket b lies in [guide[b], guide[b + 1]]
+// and a binary search over that (short) range returns exactly the leaf of
+// the search over the whole CDF.
+__global__ __launch_bounds__(256) void k_guide(const uint64_t* __restrict__ cdf, int64_t n_leaves, int g,
+                                               uint32_t* __restrict__ guide) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t G = (int64_t)1 << g;
+    if (b > G) return;
+    const uint64_t total = cdf[n_leaves - 1];
+    const uint64_t tb = b == G ? total : __umul64hi((uint64_t)b << (64 - g), total);
+    guide[b] = (uint32_t)upper_bound_u64(cdf, n_leaves, tb);
+}
+
+// The leaf drawn by the 64-bit word c0: the first with cdf > umul64hi(c0, total).
+__device__ __forceinline__ int64_t guided_leaf(const uint64_t* __restrict__ cdf, const uint32_t* __restrict__ guide,
+                                               int g, uint64_t c0, uint64_t total) {
+    const uint64_t t = __umul64hi(c0, total);
+    const uint64_t b = c0 >> (64 - g);
+    int64_t lo = guide[b], hi = guide[b + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cdf[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------- viewpoint-specific sampling
 __global__ __launch_bounds__(256) void k_sample_view(const float* __restrict__ centre,
                                                      const int32_t* __restrict__ level, float root,
                                                      const uint64_t* __restrict__ cdf, int64_t n_leaves,
+                                                     const uint32_t* __restrict__ guide, int g,
                                                      SampleCam cam, uint64_t seed0, uint64_t seed1,
                                                      int64_t n, int max_rounds, float* __restrict__ xyz,
                                                      int32_t* __restrict__ leaf_out,
@@ -272,7 +302,7 @@ __global__ __launch_bounds__(256) void k_sample_view(const float* __restrict__ c
     for (int r = 0; r < rounds; ++r) {
         uint64_t c[4] = {(uint64_t)s, (uint64_t)r, 1ull, 0ull};
         philox4x64(c, seed0, seed1);
-        leaf = upper_bound_u64(cdf, n_leaves, __umul64hi(c[0], total));
+        leaf = guided_leaf(cdf, guide, g, c[0], total);
         const float e = leaf_edge(root, clamp_level(level[leaf]));
         px = place(centre[3 * leaf], unit24(c[1]), e);
         py = place(centre[3 * leaf + 1], unit24(c[2]), e);
@@ -291,6 +321,7 @@ __global__ __launch_bounds__(256) void k_sample_view(const float* __restrict__ c
 
 // ---------------------------------------------------- global extraction
 __global__ __launch_bounds__(256) void k_sample_count(const uint64_t* __restrict__ cdf, int64_t n_leaves,
+                                                      const uint32_t* __restrict__ guide, int g,
                                                       uint64_t seed0, uint64_t seed1, int64_t n,
                                                       uint32_t* __restrict__ counts) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -299,7 +330,7 @@ __global__ __launch_bounds__(256) void k_sample_count(const uint64_t* __restrict
     if (total == 0) return;
     uint64_t c[4] = {(uint64_t)s, 0ull, 2ull, 0ull};
     philox4x64(c, seed0, seed1);
-    atomicAdd(&counts[upper_bound_u64(cdf, n_leaves, __umul64hi(c[0], total))], 1u);
+    atomicAdd(&counts[guided_leaf(cdf, guide, g, c[0], total)], 1u);
 }
 
 // Van der Corput radical inverse in base b, digit by digit in float64.
@@ -353,8 +384,11 @@ __global__ __launch_bounds__(256) void k_prob_minmax(const int32_t* __restrict__
     const int32_t l = leaf[i];
     if (l < 0 || (int64_t)l >= n_leaves) return;
     const uint32_t k = order_key(b[i]);
-    atomicMax(&kmax[l], k);
-    atomicMin(&kmin[l], k);
+    // The stored extrema only move outward, so a plain read (possibly of an
+    // older value) that already bounds k makes the atomic unnecessary; most
+    // samples of a leaf skip it.
+    if (k > kmax[l]) atomicMax(&kmax[l], k);
+    if (k < kmin[l]) atomicMin(&kmin[l], k);
 }
 
 __global__ __launch_bounds__(256) void k_prob_apply(const uint32_t* __restrict__ kmax,
@@ -388,22 +422,39 @@ void launch_sample_weights(const float* centre, const int32_t* level, const floa
     weight_scan(PhatWeight{phat, max_bits}, n_leaves, tile_sum, cdf, s);
 }
 
+int guide_bits(int64_t n_leaves) {
+    int g = 1;
+    while (((int64_t)1 << g) < n_leaves) ++g;
+    return g;
+}
+
+static void launch_guide(const uint64_t* cdf, int64_t n_leaves, uint32_t* guide, hipStream_t s) {
+    const int g = guide_bits(n_leaves);
+    hipLaunchKernelGGL(k_guide, dim3(blocks_for(((int64_t)1 << g) + 1)), dim3(256), 0, s, cdf, n_leaves, g, guide);
+}
+
 void launch_sample_view(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
-                        int64_t n_leaves, const SampleCam& cam, uint64_t seed0, uint64_t seed1, int64_t n,
-                        int max_rounds, float* xyz, int32_t* leaf, unsigned long long* unresolved, hipStream_t s) {
+                        int64_t n_leaves, uint32_t* guide, const SampleCam& cam, uint64_t seed0, uint64_t seed1,
+                        int64_t n, int max_rounds, float* xyz, int32_t* leaf, unsigned long long* unresolved,
+                        hipStream_t s) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(unresolved), 0u, 2, s);
     if (n == 0) return;
+    launch_guide(cdf, n_leaves, guide, s);
     hipLaunchKernelGGL(k_sample_view, dim3(blocks_for(n)), dim3(256), 0, s, centre, level, root, cdf, n_leaves,
-                       cam, seed0, seed1, n, max_rounds, xyz, leaf, unresolved);
+                       (const uint32_t*)guide, guide_bits(n_leaves), cam, seed0, seed1, n, max_rounds, xyz, leaf,
+                       unresolved);
 }
 
 void launch_sample_global(const float* centre, const int32_t* level, float root, const uint64_t* cdf,
-                          int64_t n_leaves, uint64_t seed0, uint64_t seed1, int64_t n, uint32_t* counts,
-                          uint64_t* tile_sum, uint64_t* count_cdf, float* xyz, int32_t* leaf, hipStream_t s) {
+                          int64_t n_leaves, uint32_t* guide, uint64_t seed0, uint64_t seed1, int64_t n,
+                          uint32_t* counts, uint64_t* tile_sum, uint64_t* count_cdf, float* xyz, int32_t* leaf,
+                          hipStream_t s) {
     launch_fill_u32(counts, 0u, (size_t)n_leaves, s);
-    if (n > 0)
-        hipLaunchKernelGGL(k_sample_count, dim3(blocks_for(n)), dim3(256), 0, s, cdf, n_leaves, seed0, seed1, n,
-                           counts);
+    if (n > 0) {
+        launch_guide(cdf, n_leaves, guide, s);
+        hipLaunchKernelGGL(k_sample_count, dim3(blocks_for(n)), dim3(256), 0, s, cdf, n_leaves,
+                           (const uint32_t*)guide, guide_bits(n_leaves), seed0, seed1, n, counts);
+    }
     weight_scan(CountWeight{counts}, n_leaves, tile_sum, count_cdf, s);
     if (n > 0)
         hipLaunchKernelGGL(k_sample_expand, dim3(blocks_for(n)), dim3(256), 0, s, centre, level, root,
