@@ -65,27 +65,48 @@ __device__ __forceinline__ TileCtx tile_ctx(const GpuView* __restrict__ views, i
     return c;
 }
 
-// LDS image of one chunk of entries: packed anchor word (tile-local x0+1,
-// y0+1, corner mask; 0 = no entry), record fields, feature rows at an odd
-// stride (entries read by different lanes then fall in different banks),
-// the forward's T_k of the entry's four splats (backward only), for every
-// pixel of the tile a bit per chunk entry that covers it, and (L > 1) every
-// pixel's covering entry slots in order, at a row stride of NT + 4 bytes.
+// LDS image of one chunk of entries: per entry a 16-byte geometry word
+// (ax, ay, opacity, and the packed anchor word: tile-local x0+1, y0+1,
+// corner mask; 0 = no entry), the view point, the feature row (rows of a
+// multiple of 4 floats at a stride of FM + 4, read with 16-byte loads; other
+// widths at an odd stride), the forward's T_k of the entry's four splats,
+// for every pixel of the tile a bit per chunk entry that covers it, and
+// (L > 1) every pixel's covering entry slots in order, at a row stride of
+// NT + 4 bytes.
 template <int TS, int L, int FM>
 struct TileChunk {
     static constexpr int NT = TileDims<TS, L>::NT;
     static constexpr int NPIX = TileDims<TS, L>::NPIX;
-    static constexpr int FS = FM | 1;                    // odd row stride in floats
+    static constexpr bool VEC = FM % 4 == 0;
+    static constexpr int FS = VEC ? FM + 4 : (FM | 1);   // feature row stride in floats
     static constexpr int BW = TileDims<TS, L>::NW + 1;   // words per pixel row of bits (odd stride)
     static constexpr int LS = L > 1 ? NT + 4 : 0;        // bytes per pixel row of entry slots
-    uint32_t hit[NT];
-    float ax[NT], ay[NT], opa[NT];
-    uint32_t vp[NT];
-    float feat[NT * FS];
+    float4 geo[NT];
     float4 tk[NT];
+    float feat[NT * FS];
+    uint32_t vp[NT];
     uint32_t bits[NPIX * BW];
     unsigned char lst[NPIX * LS + 4];
 };
+
+// Feature row of chunk entry j.
+template <int TS, int L, int FM>
+__device__ __forceinline__ void chunk_feat(const TileChunk<TS, L, FM>& S, int j, float (&v)[FM]) {
+    constexpr int FS = TileChunk<TS, L, FM>::FS;
+    if constexpr (TileChunk<TS, L, FM>::VEC) {
+        const float4* r = reinterpret_cast<const float4*>(&S.feat[j * FS]);
+#pragma unroll
+        for (int i = 0; i < FM / 4; ++i) {
+            const float4 q = r[i];
+            v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < FM; ++f) v[f] = S.feat[j * FS + f];
+    }
+}
+
+__device__ __forceinline__ uint32_t geo_hit(const float4 g) { return __float_as_uint(g.w); }
 
 // One entry held in registers between its gather and its store into LDS,
 // so that the gathers of the next chunk overlap the blending of this one.
@@ -142,12 +163,16 @@ __device__ __forceinline__ void store_entry(TileChunk<TS, L, FM>& S, const TileC
     const int i = threadIdx.x;
     uint32_t w = 0;
     if (e.valid) {
+        if constexpr (TileChunk<TS, L, FM>::VEC) {
+            float4* r = reinterpret_cast<float4*>(&S.feat[i * FS]);
 #pragma unroll
-        for (int f = 0; f < FM; ++f) S.feat[i * FS + f] = e.cf[f];
+            for (int q = 0; q < FM / 4; ++q)
+                r[q] = make_float4(e.cf[4 * q], e.cf[4 * q + 1], e.cf[4 * q + 2], e.cf[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int f = 0; f < FM; ++f) S.feat[i * FS + f] = e.cf[f];
+        }
         if constexpr (WANT_T) S.tk[i] = e.t4;
-        S.ax[i] = e.r.ax;
-        S.ay[i] = e.r.ay;
-        S.opa[i] = e.r.opa;
         S.vp[i] = e.vp;
         const int lx0 = anc_x0(e.r.anc) - c.tx * TS, ly0 = anc_y0(e.r.anc) - c.ty * TS;
         const uint32_t mask = anc_mask(e.r.anc);
@@ -159,7 +184,8 @@ __device__ __forceinline__ void store_entry(TileChunk<TS, L, FM>& S, const TileC
                 atomicOr(&S.bits[(py * TS + px) * BW + (i >> 5)], 1u << (i & 31));
         }
     }
-    S.hit[i] = w;
+    S.geo[i] = make_float4(e.valid ? e.r.ax : 0.0f, e.valid ? e.r.ay : 0.0f, e.valid ? e.r.opa : 0.0f,
+                           __uint_as_float(w));
 }
 
 template <int TS, int L, int FM>
@@ -258,7 +284,7 @@ template <int TS, int L, int FM, bool COLOUR>
 __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const TileCtx& c, uint32_t c0, int lim,
                                             int n, float tau, FwdAcc<FM>& a, float* s_tk,
                                             float* __restrict__ splat_weight) {
-    constexpr int FS = TileChunk<TS, L, FM>::FS, NW = TileDims<TS, L>::NW;
+    constexpr int NW = TileDims<TS, L>::NW;
     if constexpr (L == 1) {
 #pragma unroll
         for (int wd = 0; wd < NW; ++wd) {
@@ -266,15 +292,18 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
             while (m != 0u && !a.done) {
                 const int j = wd * 32 + (__ffs(m) - 1);
                 m &= m - 1u;
-                const int corner = corner_of(S.hit[j], c.lx, c.ly);
+                const float4 ge = S.geo[j];
+                const int corner = corner_of(geo_hit(ge), c.lx, c.ly);
                 float wx, wy, alpha, om;
-                corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
-                splat_alpha(S.opa[j], wx, wy, alpha, om);
+                corner_factors(ge.x, ge.y, corner, wx, wy);
+                splat_alpha(ge.z, wx, wy, alpha, om);
                 const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
                 if constexpr (COLOUR) {
                     const float ta = a.T * alpha;
+                    float cf[FM];
+                    chunk_feat(S, j, cf);
 #pragma unroll
-                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
+                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, cf[f], a.C[f]);
                     if (splat_weight) splat_weight[id] = ta;
                 }
                 if (s_tk) s_tk[4 * j + corner] = a.T;
@@ -293,10 +322,11 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
             float alpha = 0.0f, om = 1.0f;
             int corner = 0;
             if (valid) {
-                corner = corner_of(S.hit[j], c.lx, c.ly);
+                const float4 ge = S.geo[j];
+                corner = corner_of(geo_hit(ge), c.lx, c.ly);
                 float wx, wy;
-                corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
-                splat_alpha(S.opa[j], wx, wy, alpha, om);
+                corner_factors(ge.x, ge.y, corner, wx, wy);
+                splat_alpha(ge.z, wx, wy, alpha, om);
             }
             const GroupStep g = group_step<L>(a.T, om, valid, !a.started && c.sub == 0, tau, c.sub);
             a.started = true;
@@ -304,8 +334,10 @@ __device__ __forceinline__ void blend_chunk(const TileChunk<TS, L, FM>& S, const
                 const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
                 if constexpr (COLOUR) {
                     const float ta = g.tb * alpha;
+                    float cf[FM];
+                    chunk_feat(S, j, cf);
 #pragma unroll
-                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, S.feat[j * FS + f], a.C[f]);
+                    for (int f = 0; f < FM; ++f) a.C[f] = __builtin_fmaf(ta, cf[f], a.C[f]);
                     if (splat_weight) splat_weight[id] = ta;
                 }
                 if (s_tk) s_tk[4 * j + corner] = g.tb;
@@ -386,7 +418,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
     const uint32_t* __restrict__ vals, const unsigned char* __restrict__ payload, int ps, int Fd,
     float tau, const PixelState* __restrict__ state, const float* __restrict__ g_img,
     const float* __restrict__ g_t, float4* __restrict__ t_ent, int rebuild_t, float2* __restrict__ frec) {
-    constexpr int FS = TileChunk<TS, L, FM>::FS, NT = TileDims<TS, L>::NT, NW = TileDims<TS, L>::NW;
+    constexpr int NT = TileDims<TS, L>::NT, NW = TileDims<TS, L>::NW;
     __shared__ TileChunk<TS, L, FM> S;
     __shared__ uint32_t s_last;
     const TileCtx c = tile_ctx<TS, L>(views, n_views, perm);
@@ -462,15 +494,17 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                         const int b = 31 - __clz(m);
                         m &= ~(1u << b);
                         const int j = wd * 32 + b;
-                        const int corner = corner_of(S.hit[j], c.lx, c.ly);
+                        const float4 ge = S.geo[j];
+                        const int corner = corner_of(geo_hit(ge), c.lx, c.ly);
                         float wx, wy;
-                        corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
+                        corner_factors(ge.x, ge.y, corner, wx, wy);
                         const uint32_t id = 4u * S.vp[j] + (uint32_t)corner;
-                        const double alpha = (double)S.opa[j] * ((double)wx * (double)wy);
+                        const double alpha = (double)ge.z * ((double)wx * (double)wy);
+                        float cf[FM];
+                        chunk_feat(S, j, cf);
                         double gc = 0.0;
 #pragma unroll
-                        for (int f = 0; f < FM; ++f)
-                            gc = __builtin_fma((double)g[f], (double)S.feat[j * FS + f], gc);
+                        for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)cf[f], gc);
                         const float4 t4 = S.tk[j];
                         const double Tk =
                             (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
@@ -491,13 +525,16 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                 uint32_t id = 0;
                 if (valid) {
                     const int j = (int)lst[kk];
-                    const int corner = corner_of(S.hit[j], c.lx, c.ly);
+                    const float4 ge = S.geo[j];
+                    const int corner = corner_of(geo_hit(ge), c.lx, c.ly);
                     float wx, wy;
-                    corner_factors(S.ax[j], S.ay[j], corner, wx, wy);
+                    corner_factors(ge.x, ge.y, corner, wx, wy);
                     id = 4u * S.vp[j] + (uint32_t)corner;
-                    alpha = (double)S.opa[j] * ((double)wx * (double)wy);
+                    alpha = (double)ge.z * ((double)wx * (double)wy);
+                    float cf[FM];
+                    chunk_feat(S, j, cf);
 #pragma unroll
-                    for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)S.feat[j * FS + f], gc);
+                    for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)cf[f], gc);
                     const float4 t4 = S.tk[j];
                     Tk = (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
                     A = alpha * gc;
