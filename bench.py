@@ -271,6 +271,13 @@ def main():
     achieved = model[dom] / (dom_ms * 1e-3) / 1e9
     total_model = sum(model[k] for k in leaf)
     traffic = measured_traffic(dom, launches)
+    # measured HBM rate of the stages that run one kernel per launch
+    counter_gbs = {}
+    for k in ("project", "blend_fwd", "blend_bwd", "point_reduce"):
+        if k in per_step:
+            b = measured_traffic(k, per_step[k][1])
+            if b is not None and per_step[k][0] > 0:
+                counter_gbs[k] = round(b / (per_step[k][0] * 1e-3) / 1e9, 1)
     roofline = {
         "bound": "hbm", "kernel": dom, "launches_per_step": launches,
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -299,6 +306,7 @@ def main():
                    else "per-pixel splat lists", "list_items": items,
                    "t_threshold": 1e-4, "tuning": tn[tid]},
         "model_gbs": round(total_model / (ms_per_step * 1e-3) / 1e9, 1),
+        "counter_gbs": counter_gbs or None,
         "stages_ms_per_step": {k: round(v[0], 4) for k, v in per_step.items()},
         "roofline": roofline,
     }
@@ -316,6 +324,20 @@ def main():
             "kind": "oracle",
             "sample": f"whole workload once: {L.m} fragments, fwd+bwd in {dt:.2f} s",
         }
+        del L, fw
+        # the same on one thread, on the first eighth of the points
+        threads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        n1 = s.n // 8
+        t0 = time.perf_counter()
+        L = oracle.fragments(s.xyz[:n1], s.cam)
+        fw = oracle.blend_forward(L, s.opa[:n1], s.feat[:n1], 1e-4)
+        oracle.blend_backward(L, s.opa[:n1], s.feat[:n1], fw["n_blended"], s.g_img)
+        dt1 = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
+        result["cpu_baseline"]["one_thread"] = {
+            "value": round(L.m / dt1, 1), "unit": "fragments/s", "cores": 1,
+            "sample": f"first {n1} points of the workload: {L.m} fragments, fwd+bwd in {dt1:.2f} s"}
         del L, fw
 
     if not args.no_next:

@@ -59,12 +59,19 @@ def lib():
         L.orc_blend_weight.argtypes = [i64, P, P, P, P, P, i64, P]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel regions (timing runs only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _cam(cam) -> _Camera:
