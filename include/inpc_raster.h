@@ -7,8 +7,10 @@
  *      against the near/far planes and the image;
  *   2. splat it to the 2x2 pixels whose centres are closest to (u, v) with
  *      opacity alpha = alpha_h (1-|u-u_i|)(1-|v-v_i|) (Section 3.4, Eq. 6);
- *   3. order each pixel's splats by depth with one global sort of
- *      (pixel, depth) keys;
+ *   3. order each pixel's splats by depth with one global sort: of
+ *      (pixel, depth) keys, or (default) of (tile, depth) keys over one entry
+ *      per (8x8 pixel tile, point) pair, whose order restricted to a pixel is
+ *      that pixel's depth order;
  *   4. blend each pixel front to back, C = sum_i T_i alpha_i c_i,
  *      T_i = prod_{j<i} (1 - alpha_j) (Eq. 1), stopping after the splat that
  *      drops T below the threshold (Appendix A.6: 1e-4);
@@ -289,8 +291,9 @@ int inpc_sum_view_grads(const inpc_view_t *views_host, int32_t n_views, int64_t 
 
 /* What a forward stored (synchronises the stream): *stored_items = number of
  * list items (splats for per-pixel lists, tile entries for tile lists) and
- * *layout = 0 for per-pixel lists or the tile-list blend shape (5: 16x16,
- * 6: 8x8 tiles).  Arguments as for inpc_debug_fragments. */
+ * *layout = 0 for per-pixel lists or the tile-list blend shape (5: 16x16
+ * tiles; 6, 7, 8: 8x8 tiles with 1, 4 or 2 lanes per pixel).  Arguments as
+ * for inpc_debug_fragments. */
 int inpc_state_info(const inpc_view_t *views_host, int32_t n_views, int64_t n_points, int32_t F,
                     int32_t feat_dtype, const void *saved, size_t saved_bytes,
                     int64_t *stored_items, int32_t *layout, void *stream);
