@@ -61,6 +61,21 @@ def test_tile_ragged_sizes_and_feature_widths(which):
 
 
 @pytest.mark.parametrize("which", VARIANTS)
+def test_tile_bf16_ragged_feature_widths(which):
+    """bfloat16 features of widths without a vector path (3, 20) and a
+    compiled one (16) on ragged image sizes."""
+    tid = tuning_named(which)
+    for (W, Hh, F) in [(37, 23, 3), (211, 97, 20), (64, 64, 16)]:
+        rng = np.random.default_rng(W + 31 * Hh)
+        cam = workloads.canonical_camera(W, Hh)
+        n = 15_000
+        xyz = workloads.scenes.cluster_points(rng, n, 6, cam).astype(np.float32)
+        feat = rng.uniform(0, 1, (n, F)).astype(np.float32)
+        opa = rng.uniform(0.05, 0.95, n).astype(np.float32)
+        _scene_case(xyz, feat, opa, cam, tuning_id=tid, seed=W, bf16=True)
+
+
+@pytest.mark.parametrize("which", VARIANTS)
 def test_tile_tau_zero_opaque_and_gt(which):
     tid = tuning_named(which)
     rng = np.random.default_rng(5)
