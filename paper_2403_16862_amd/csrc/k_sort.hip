@@ -17,6 +17,7 @@
 namespace inpc {
 
 constexpr int kSortBlock = 256;
+constexpr uint32_t kXcdGroup = 8;   // consecutive downsweep tiles per XCD
 
 static inline size_t tiles_for(int items, int64_t n) {
     const int64_t tile = (int64_t)kSortBlock * items;
@@ -125,7 +126,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     __shared__ uint32_t s_tmp[WAVES];
 
     const uint32_t n = live_count(n_dev, n_bound);
-    const uint32_t tile = blockIdx.x;
+    // Runs of consecutive groups of kXcdGroup tiles go to one XCD (blocks are
+    // dealt to the 8 XCDs round-robin): a digit's runs of neighbouring tiles
+    // are adjacent in the output, so they meet in one L2 and leave it as
+    // whole lines.
+    const uint32_t k8 = blockIdx.x >> 3;
+    const uint32_t tile = ((k8 / kXcdGroup) * 8u + (blockIdx.x & 7u)) * kXcdGroup + (k8 % kXcdGroup);
     if ((uint64_t)tile * TILE >= n) return;
     for (int i = threadIdx.x; i < WAVES * BINS; i += kSortBlock) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
@@ -235,7 +241,8 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     }
     {
         ProfScope p(kStSortDownsweep, s);
-        hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+        const size_t grid = (tiles + 8 * kXcdGroup - 1) / (8 * kXcdGroup) * (8 * kXcdGroup);
+        hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
                            kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals);
     }
 }
