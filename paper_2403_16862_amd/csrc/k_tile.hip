@@ -155,34 +155,58 @@ __device__ __forceinline__ void fetch_entry(EntryRegs<FM>& e, uint32_t c0, uint3
     }
 }
 
+// The two halves of fetch_entry for the software-pipelined chunk loops: a
+// chunk's view points are loaded one chunk before its payload rows, so each
+// chunk waits on one memory latency instead of two dependent ones.  Both
+// loads are issued by every lane (indices past ``end`` are clamped to the
+// tile's last entry, whose row is a real one): a load that some paths skip
+// would make the compiler wait for every older memory operation instead of
+// the ones it needs.  The tile must be non-empty (lo < end) in entry_vp_in.
+__device__ __forceinline__ uint32_t entry_vp_in(uint32_t c0, uint32_t end, const uint32_t* __restrict__ vals) {
+    const uint32_t j = c0 + threadIdx.x;
+    return vals[j < end ? j : end - 1u];
+}
+
+template <typename FT, int FM, bool DYN, bool WANT_T>
+__device__ __forceinline__ void fetch_entry_of(EntryRegs<FM>& e, uint32_t vp, uint32_t c0, uint32_t end,
+                                               const unsigned char* __restrict__ payload, int ps, int Fd,
+                                               const float4* __restrict__ t_ent) {
+    const uint32_t j = c0 + threadIdx.x;
+    e.valid = c0 < end && j < end;
+    e.vp = vp;
+    const unsigned char* row = payload + (size_t)vp * ps;
+    e.r = *reinterpret_cast<const PointRec*>(row);
+    payload_feat<FT, FM, DYN>(reinterpret_cast<const FT*>(row + sizeof(PointRec)), Fd, e.cf);
+    if constexpr (WANT_T) e.t4 = t_ent[j < end ? j : end - 1u];
+}
+
 // Thread i stores its entry and marks the (at most four) pixels of the tile
-// its splats cover; ``bits`` must be cleared before.
+// its splats cover; ``bits`` must be cleared before.  Every lane writes its
+// slot (an invalid entry covers no pixel), without a branch around the use of
+// the loaded values, so the compiler's wait for them holds on every path.
 template <int TS, int L, int FM, bool WANT_T>
 __device__ __forceinline__ void store_entry(TileChunk<TS, L, FM>& S, const TileCtx& c, const EntryRegs<FM>& e) {
     constexpr int FS = TileChunk<TS, L, FM>::FS, BW = TileChunk<TS, L, FM>::BW;
     const int i = threadIdx.x;
-    uint32_t w = 0;
-    if (e.valid) {
-        if constexpr (TileChunk<TS, L, FM>::VEC) {
-            float4* r = reinterpret_cast<float4*>(&S.feat[i * FS]);
+    if constexpr (TileChunk<TS, L, FM>::VEC) {
+        float4* r = reinterpret_cast<float4*>(&S.feat[i * FS]);
 #pragma unroll
-            for (int q = 0; q < FM / 4; ++q)
-                r[q] = make_float4(e.cf[4 * q], e.cf[4 * q + 1], e.cf[4 * q + 2], e.cf[4 * q + 3]);
-        } else {
+        for (int q = 0; q < FM / 4; ++q)
+            r[q] = make_float4(e.cf[4 * q], e.cf[4 * q + 1], e.cf[4 * q + 2], e.cf[4 * q + 3]);
+    } else {
 #pragma unroll
-            for (int f = 0; f < FM; ++f) S.feat[i * FS + f] = e.cf[f];
-        }
-        if constexpr (WANT_T) S.tk[i] = e.t4;
-        S.vp[i] = e.vp;
-        const int lx0 = anc_x0(e.r.anc) - c.tx * TS, ly0 = anc_y0(e.r.anc) - c.ty * TS;
-        const uint32_t mask = anc_mask(e.r.anc);
-        w = (uint32_t)(lx0 + 1) | ((uint32_t)(ly0 + 1) << 5) | (mask << 10);
+        for (int f = 0; f < FM; ++f) S.feat[i * FS + f] = e.cf[f];
+    }
+    if constexpr (WANT_T) S.tk[i] = e.t4;
+    S.vp[i] = e.vp;
+    const int lx0 = anc_x0(e.r.anc) - c.tx * TS, ly0 = anc_y0(e.r.anc) - c.ty * TS;
+    const uint32_t mask = e.valid ? anc_mask(e.r.anc) : 0u;
+    const uint32_t w = e.valid ? (uint32_t)(lx0 + 1) | ((uint32_t)(ly0 + 1) << 5) | (mask << 10) : 0u;
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
-            const int px = lx0 + (cc & 1), py = ly0 + (cc >> 1);
-            if (((mask >> cc) & 1u) && (unsigned)px < (unsigned)TS && (unsigned)py < (unsigned)TS)
-                atomicOr(&S.bits[(py * TS + px) * BW + (i >> 5)], 1u << (i & 31));
-        }
+    for (int cc = 0; cc < 4; ++cc) {
+        const int px = lx0 + (cc & 1), py = ly0 + (cc >> 1);
+        if (((mask >> cc) & 1u) && (unsigned)px < (unsigned)TS && (unsigned)py < (unsigned)TS)
+            atomicOr(&S.bits[(py * TS + px) * BW + (i >> 5)], 1u << (i & 31));
     }
     S.geo[i] = make_float4(e.valid ? e.r.ax : 0.0f, e.valid ? e.r.ay : 0.0f, e.valid ? e.r.opa : 0.0f,
                            __uint_as_float(w));
@@ -368,22 +392,37 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
     const uint2 r = range[c.tile];
     FwdAcc<FM> a;
     fwd_init(a, !c.inside);
-    EntryRegs<FM> e;
+    EntryRegs<FM> e{};   // invalid entries keep defined (zero) values
     fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
     if constexpr (L > 1) {
         // from here on compact_cover clears the bits it has read
         clear_bits<TS, L, FM>(S);
         __syncthreads();
     }
-    for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
+    // The T_k of a chunk's entries are stored (by entry, coalesced) at the
+    // start of the next chunk, before its loads are issued, so that the loads
+    // are always the youngest memory operations and waiting for them waits
+    // for nothing else.  Only the last chunk can be partial; it is stored
+    // after the loop.
+    uint32_t c_last = r.x;
+    // One chunk: vcur holds the view points of the next chunk; returns the
+    // ones of the chunk after it, and sets ``stop`` once every pixel of the
+    // tile has terminated.
+    bool stop = false;
+    auto chunk = [&](uint32_t c0, uint32_t vcur) -> uint32_t {
         if constexpr (L == 1) {
             clear_bits<TS, L, FM>(S);
             __syncthreads();
         }
         store_entry<TS, L, FM, false>(S, c, e);
-        if (s_tk) S.tk[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (s_tk) {
+            if (c0 > r.x) t_ent[c0 - NT + threadIdx.x] = S.tk[threadIdx.x];
+            S.tk[threadIdx.x] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
         __syncthreads();
-        fetch_entry<FT, FM, DYN, false>(e, c0 + NT, r.y, vals, payload, ps, Fd, nullptr);
+        c_last = c0;
+        const uint32_t vnext = entry_vp_in(c0 + 2 * NT, r.y, vals);
+        fetch_entry_of<FT, FM, DYN, false>(e, vcur, c0 + NT, r.y, payload, ps, Fd, nullptr);
         const int lim = (int)(r.y - c0);
         int n = 0;
         if constexpr (L > 1) {
@@ -391,11 +430,12 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_fwd(
             __syncthreads();
         }
         if (!a.done) blend_chunk<TS, L, FM, true>(S, c, c0, lim, n, tau, a, s_tk, splat_weight);
-        const bool all_done = __syncthreads_and(a.done ? 1 : 0);
-        // the T_k of the chunk's entries, by entry (coalesced)
-        if (s_tk && c0 + threadIdx.x < r.y) t_ent[c0 + threadIdx.x] = S.tk[threadIdx.x];
-        if (all_done) break;
-    }
+        stop = __syncthreads_and(a.done ? 1 : 0);
+        return vnext;
+    };
+    uint32_t vn = r.x < r.y ? entry_vp_in(r.x + NT, r.y, vals) : 0u;
+    for (uint32_t c0 = r.x; c0 < r.y && !stop; c0 += NT) vn = chunk(c0, vn);
+    if (s_tk && r.x < r.y && c_last + threadIdx.x < r.y) t_ent[c_last + threadIdx.x] = S.tk[threadIdx.x];
 #pragma unroll
     for (int mm = L / 2; mm >= 1; mm >>= 1) {
 #pragma unroll
@@ -432,7 +472,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
         // T_k by the forward's own recurrence (same operations, same order).
         FwdAcc<FM> a;
         fwd_init(a, !c.inside);
-        EntryRegs<FM> e;
+        EntryRegs<FM> e{};   // invalid entries keep defined (zero) values
         fetch_entry<FT, FM, DYN, false>(e, r.x, r.y, vals, payload, ps, Fd, nullptr);
         for (uint32_t c0 = r.x; c0 < r.y; c0 += NT) {
             if constexpr (L == 1) {
@@ -471,7 +511,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
         for (int f = 0; f < FM; ++f) g[f] = 0.0f;
     }
     const uint32_t n_chunks = (lmax - r.x + NT - 1) / NT;
-    EntryRegs<FM> e;
+    EntryRegs<FM> e{};   // invalid entries keep defined (zero) values
     fetch_entry<FT, FM, DYN, true>(e, r.x + (n_chunks - 1) * NT, r.y, vals, payload, ps, Fd, t_ent);
     for (int k = (int)n_chunks - 1; k >= 0; --k) {
         const uint32_t c0 = r.x + (uint32_t)k * NT;
