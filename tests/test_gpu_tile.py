@@ -115,9 +115,8 @@ def test_tile_recompute_equals_save(which):
 def test_tile_matches_list_path_closely(which, mode):
     """Same fragments, same per-pixel float32 recurrence as the 1-lane list
     blend: images agree bit for bit with tuning '1 lane/pixel', and so do the
-    gradients (the backward's per-splat float64 chain is the same, and the
-    points combined inside the tile backward use the per-point reduction's
-    operations in its order)."""
+    gradients (the backward's per-splat float64 chain is the same, and both
+    paths combine the per-splat records with the same per-point reduction)."""
     one = [i for i, n in enumerate(pr.tuning_table()) if "1 lane/pixel 8x8" in n][0]
     tid = tuning_named(which)
     s = workloads.config2(n=300_000)
@@ -170,3 +169,63 @@ def test_tile_batched_views_graph(which):
         rb = oracle.blend_backward(L, b.opa[sl], fbits[sl], n_gpu, g[lo:hi])
         H.check_grads(gf[vp_off[v]:vp_off[v + 1]], go[vp_off[v]:vp_off[v + 1]], rb)
         H.check_blend_weight(bw[vp_off[v]:vp_off[v + 1]], L, b.opa[sl], n_gpu)
+
+
+# entries per 8x8 tile around the chunk sizes of the tile blends (64 entries
+# per chunk with one lane per 8x8 pixel, 256 with 4 lanes or 16x16 tiles)
+CHUNK_COUNTS = [1, 63, 64, 65, 127, 128, 129, 255, 256, 257, 513]
+
+
+def _chunk_boundary_scene(seed):
+    """Points placed so that 8x8 tile i of a 96x64 image (first tile row) is
+    touched by exactly CHUNK_COUNTS[i] points, every 2x2 footprint inside its
+    tile; the other tiles are empty.  Checked against the oracle's splats."""
+    W, Hh = 96, 64
+    cam = workloads.canonical_camera(W, Hh)
+    rng = np.random.default_rng(seed)
+    pts = []
+    for i, n in enumerate(CHUNK_COUNTS):
+        u = i * 8 + rng.uniform(1.5, 6.5, n)
+        v = rng.uniform(1.5, 6.5, n)
+        z = rng.uniform(2.0, 10.0, n)
+        pts.append(np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], 1))
+    xyz = np.concatenate(pts)[rng.permutation(sum(CHUNK_COUNTS))].astype(np.float32)
+    pix, _, ids, _ = oracle.emit(xyz, cam)
+    tile = (pix // W // 8) * (W // 8) + (pix % W) // 8
+    pairs = np.unique(tile.astype(np.int64) * (1 << 32) + ids // 4)
+    counts = np.bincount(pairs >> 32, minlength=(W // 8) * (Hh // 8))
+    assert list(counts[:len(CHUNK_COUNTS)]) == CHUNK_COUNTS and not counts[len(CHUNK_COUNTS):].any()
+    return xyz, cam
+
+
+@pytest.mark.parametrize("which", VARIANTS)
+def test_tile_chunk_boundaries(which):
+    """Tiles whose entry counts sit on, just below and just above multiples
+    of the chunk size (the prefetch of the next chunk's view points and rows
+    clamps its indices at the tile's end), with faint splats (every chunk is
+    walked) and with dense ones (pixels terminate inside the tile)."""
+    tid = tuning_named(which)
+    xyz, cam = _chunk_boundary_scene(11)
+    rng = np.random.default_rng(12)
+    n = xyz.shape[0]
+    feat = rng.uniform(0, 1, (n, 16)).astype(np.float32)
+    for lo, hi in [(0.01, 0.05), (0.3, 0.95)]:
+        opa = rng.uniform(lo, hi, n).astype(np.float32)
+        _scene_case(xyz, feat, opa, cam, tuning_id=tid, seed=int(100 * hi), g_t=True)
+
+
+@pytest.mark.parametrize("which", ONE_LANE)
+def test_tile_chunk_boundaries_match_list_path(which):
+    one = [i for i, n in enumerate(pr.tuning_table()) if "1 lane/pixel 8x8" in n][0]
+    tid = tuning_named(which)
+    xyz, cam = _chunk_boundary_scene(13)
+    rng = np.random.default_rng(14)
+    n = xyz.shape[0]
+    feat = rng.uniform(0, 1, (n, 16)).astype(np.float32)
+    opa = rng.uniform(0.01, 0.3, n).astype(np.float32)
+    g = rng.normal(size=(cam.height * cam.width, 16)).astype(np.float32)
+    a = H.gpu_forward(xyz, feat, opa, cam, tuning_id=one)
+    b = H.gpu_forward(xyz, feat, opa, cam, tuning_id=tid)
+    assert torch.equal(a["image"], b["image"]) and torch.equal(a["t_final"], b["t_final"])
+    ga, gb = H.gpu_backward(a, g), H.gpu_backward(b, g)
+    assert np.array_equal(ga[0], gb[0]) and np.array_equal(ga[1], gb[1])
