@@ -19,35 +19,68 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     float* __restrict__ grad_feat, float* __restrict__ grad_opa, float* __restrict__ blend_weight) {
     const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (vp >= n_vp) return;
+    // The point's record, its four splat records (zero where nothing was
+    // blended) and its view's placement are read together, and for narrow
+    // rows the gradient rows of all corners are in flight before the first
+    // one is used: each point waits on two memory latencies, not one per
+    // read.  No load sits under a branch (a point without splats reads its
+    // view's first pixel row and ignores it), so the compiler cannot sink the
+    // record loads behind the wait for the point record.
+    const int v = n_views == 1 ? 0
+                               : find_view(views, n_views, vp, [](const GpuView& g) { return g.vpoint_offset; });
+    const int64_t pix0 = views[v].pixel_offset;
+    const int64_t W = views[v].W;
     const PointRec pr = rec[vp];
+    const float4 r01 = reinterpret_cast<const float4*>(frec)[2 * vp];
+    const float4 r23 = reinterpret_cast<const float4*>(frec)[2 * vp + 1];
     const uint32_t mask = anc_mask(pr.anc);
+    const float da[4] = {r01.x, r01.z, r23.x, r23.z};
+    const float ta[4] = {r01.y, r01.w, r23.y, r23.w};
+    // pixel of each corner; a missing corner (off the image or of zero
+    // weight) reads the row of the first present one
+    const int x0 = anc_x0(pr.anc), y0 = anc_y0(pr.anc);
+    const int cf = mask != 0u ? __builtin_ctz(mask) : 0;
+    int64_t q[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int cc = ((mask >> c) & 1u) ? c : cf;
+        q[c] = mask != 0u ? pix0 + (int64_t)(y0 + (cc >> 1)) * W + (x0 + (cc & 1)) : pix0;
+    }
     // float64 accumulators: the (at most four) corner terms often cancel.
     double gf[FM];
 #pragma unroll
     for (int f = 0; f < FM; ++f) gf[f] = 0.0;
     double go = 0.0, bw = 0.0;
-    if (mask != 0u) {
-        const int v = n_views == 1 ? 0
-                                   : find_view(views, n_views, vp,
-                                               [](const GpuView& g) { return g.vpoint_offset; });
-        const GpuView& V = views[v];
-        const int x0 = anc_x0(pr.anc), y0 = anc_y0(pr.anc);
-        const float4 r01 = reinterpret_cast<const float4*>(frec)[2 * vp];
-        const float4 r23 = reinterpret_cast<const float4*>(frec)[2 * vp + 1];
-        const float da[4] = {r01.x, r01.z, r23.x, r23.z};
-        const float ta[4] = {r01.y, r01.w, r23.y, r23.w};
+    // the terms of corner c, kept only if the corner exists (a select, so
+    // the result equals skipping the corner bit for bit, and the row's loads
+    // have a use on every path)
+    auto corner_terms = [&](int c, const float (&g)[FM]) {
+        const bool on = (mask >> c) & 1u;
+        float wx, wy;
+        corner_factors(pr.ax, pr.ay, c, wx, wy);
+        const double go2 = __builtin_fma((double)wx * (double)wy, (double)da[c], go);
+        const double bw2 = __builtin_fma((double)wx * (double)wy, (double)ta[c], bw);
+        go = on ? go2 : go;
+        bw = on ? bw2 : bw;
+#pragma unroll
+        for (int f = 0; f < FM; ++f) {
+            const double t = __builtin_fma((double)ta[c], (double)g[f], gf[f]);
+            gf[f] = on ? t : gf[f];
+        }
+    };
+    if constexpr (FM <= 16) {
+        float g[4][FM];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) f32_row<FM, DYN>(g_img, q[c], Fd, g[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) corner_terms(c, g[c]);
+    } else {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!((mask >> c) & 1u)) continue;
-            float wx, wy;
-            corner_factors(pr.ax, pr.ay, c, wx, wy);
-            go = __builtin_fma((double)wx * (double)wy, (double)da[c], go);
-            bw = __builtin_fma((double)wx * (double)wy, (double)ta[c], bw);
-            const int64_t q = V.pixel_offset + (int64_t)(y0 + (c >> 1)) * V.W + (x0 + (c & 1));
             float g[FM];
-            f32_row<FM, DYN>(g_img, q, Fd, g);
-#pragma unroll
-            for (int f = 0; f < FM; ++f) gf[f] = __builtin_fma((double)ta[c], (double)g[f], gf[f]);
+            f32_row<FM, DYN>(g_img, q[c], Fd, g);
+            corner_terms(c, g);
         }
     }
     float out[FM];
