@@ -545,9 +545,8 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                         double gc = 0.0;
 #pragma unroll
                         for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)cf[f], gc);
-                        const float4 t4 = S.tk[j];
-                        const double Tk =
-                            (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
+                        // T_k of this corner: one LDS word at a computed address
+                        const double Tk = (double)reinterpret_cast<const float*>(S.tk)[4 * j + corner];
                         frec[id] = make_float2((float)(Tk * (gc - Y)), (float)(Tk * alpha));
                         Y = __builtin_fma(1.0 - alpha, Y, alpha * gc);
                     }
@@ -575,8 +574,7 @@ __global__ __launch_bounds__(TS * TS * L) void k_tile_bwd(
                     chunk_feat(S, j, cf);
 #pragma unroll
                     for (int f = 0; f < FM; ++f) gc = __builtin_fma((double)g[f], (double)cf[f], gc);
-                    const float4 t4 = S.tk[j];
-                    Tk = (double)(corner == 0 ? t4.x : corner == 1 ? t4.y : corner == 2 ? t4.z : t4.w);
+                    Tk = (double)reinterpret_cast<const float*>(S.tk)[4 * j + corner];
                     A = alpha * gc;
                     B = 1.0 - alpha;
                 }
