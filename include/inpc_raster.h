@@ -44,7 +44,12 @@
  *   - No gradient flows to positions or cameras (INPC samples positions
  *     rather than optimising them, Section 3.2).
  *   - The library keeps no state between calls except the autotuner's cache
- *     (guarded by a mutex); all entry points are reentrant.
+ *     and, per ``saved`` buffer, the tuning id of the last forward that
+ *     filled it (both guarded by a mutex); all entry points are reentrant.
+ *   - A backward reads its state with the tuning of the forward that filled
+ *     ``saved``: with settings.tuning_id = -1 it takes that recorded id (not
+ *     the autotuner's current choice); an explicit id that differs from the
+ *     recorded one is rejected with INPC_EINVAL.
  */
 #ifndef INPC_RASTER_H
 #define INPC_RASTER_H
@@ -154,7 +159,10 @@ int inpc_rasterize_bwd(const float *xyz, const void *feat, int32_t feat_dtype,
 
 /* Forward over several views of uneven size and point count in one launch
  * sequence: one projection, one global depth sort, one fragment emission,
- * one global pixel sort and one blend for all views.  Packed outputs:
+ * one global pixel sort and one blend for all views.  This is the shape of
+ * the paper's multisampled rendering (Section 3.2, viewpoint-specific
+ * sampling: several clouds per frame; Table 2: 4 x 8M points per frame) and
+ * of rendering several training views at once.  Packed outputs:
  * image [sum P_v, F], t_final [sum P_v], blend_weight (NULL or one entry per
  * view point, in view order) [sum point_count_v].  n_points is the length of the
  * point arrays.  The view table is read on the host and passed to the
@@ -166,7 +174,10 @@ int inpc_rasterize_fwd_batched(const float *xyz, const void *feat, int32_t feat_
                                float *t_final, float *blend_weight, void *saved,
                                size_t saved_bytes, void *ws, size_t ws_bytes, void *stream);
 
-/* Backward of the batched forward.  Gradients are per *view point*: row
+/* Backward of the batched forward (per-splat gradients in forward order,
+ * combined per point with the bilinear weights, Appendix A.6, for every view
+ * of the batch; Section 3.2's multisampling shares points between views).
+ * Gradients are per *view point*: row
  * (sum_{u<v} point_count_u) + i belongs to point point_offset_v + i of view
  * v, so grad_feat is [sum_v point_count_v, F] and grad_opacity
  * [sum_v point_count_v].  inpc_sum_view_grads() folds them onto the points. */
@@ -325,6 +336,14 @@ int inpc_autotune_load(const char *cache_path);
 /* Tuning id the library uses for this problem when settings.tuning_id == -1. */
 int inpc_tuning_for(const inpc_view_t *views_host, int32_t n_views, int64_t n_points, int32_t F,
                     int32_t feat_dtype);
+
+/* Tuning id of the last forward (plain or batched) that accepted ``saved``
+ * (a device pointer, compared by address only and never dereferenced; the id
+ * is recorded once the arguments pass validation, before the forward's work
+ * is enqueued), or INPC_EINVAL if no forward of this process recorded one
+ * (NULL, or the record was dropped after 4096 newer buffers).  Host only; no
+ * device work. */
+int inpc_saved_tuning(const void *saved);
 
 /* ------------------------------------------------------ test/debug hooks */
 

@@ -100,6 +100,7 @@ def lib():
                           i32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_float), P],
         "inpc_autotune_load": [ctypes.c_char_p],
         "inpc_tuning_for": [view_p, i32, i64, i32, i32],
+        "inpc_saved_tuning": [P],
         "inpc_debug_fragments": [view_p, i32, i64, i32, i32, P, sz, P, sz, P, P, i64,
                                  ctypes.POINTER(ctypes.c_int64), P, P],
         "inpc_state_info": [view_p, i32, i64, i32, i32, P, sz, ctypes.POINTER(ctypes.c_int64),
@@ -308,6 +309,8 @@ def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_
                                             _ptr(blend_weight), _ptr(saved), saved.numel(), _ptr(ws),
                                             ws.numel(), _stream()),
            "inpc_rasterize_fwd")
+    # the backward reads the state with the tuning this forward used
+    st.tuning_id = _check(lib().inpc_saved_tuning(_ptr(saved)), "inpc_saved_tuning")
     state = ForwardState(saved, ws if keep_workspace else None, st, views, n_views, N, F, fdt)
     return image, t_final, state
 

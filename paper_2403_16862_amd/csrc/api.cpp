@@ -92,6 +92,11 @@ struct Problem {
 
 static bool finite_f(float x) { return std::isfinite(x); }
 
+// A near plane of -0.0 keeps the same points as +0.0, but its bit pattern
+// (0x80000000) would become the base of the depth keys and wrap them, so it
+// is replaced by +0.0 before it is used anywhere.
+static float canonical_near(float n) { return n == 0.0f ? 0.0f : n; }
+
 static int check_camera(const inpc_camera_t& c) {
     if (c.width < 1 || c.height < 1) return INPC_EINVAL;
     if (c.width > 16383 || c.height > 16383) return INPC_EUNSUPPORTED;
@@ -131,7 +136,7 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
         std::memcpy(g.R, in.cam.R, sizeof g.R);
         std::memcpy(g.t, in.cam.t, sizeof g.t);
         g.fx = in.cam.fx; g.fy = in.cam.fy; g.cx = in.cam.cx; g.cy = in.cam.cy;
-        g.near_p = in.cam.near_plane; g.far_p = in.cam.far_plane;
+        g.near_p = canonical_near(in.cam.near_plane); g.far_p = in.cam.far_plane;
         g.W = in.cam.width; g.H = in.cam.height;
         g.point_offset = in.point_offset;
         g.vpoint_offset = vp;
@@ -169,7 +174,8 @@ static int make_problem(const inpc_view_t* views, int n_views, int64_t n_points,
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
     for (int v = 0; v < n_views; ++v) {
         uint32_t bn, bf;
-        std::memcpy(&bn, &views[v].cam.near_plane, 4);
+        const float nc = canonical_near(views[v].cam.near_plane);
+        std::memcpy(&bn, &nc, 4);
         std::memcpy(&bf, &views[v].cam.far_plane, 4);
         lo = std::min(lo, bn);
         hi = std::max(hi, bf);
@@ -352,6 +358,38 @@ static int resolve_tuning(int requested, const Problem& pb) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(bucket_key(pb));
     return it == g_tune_cache.end() ? kDefaultTuning : it->second;
+}
+
+// ------------------------------------------- tuning of each saved state
+// The tuning id a forward used, keyed by its ``saved`` buffer.  The tuning
+// fixes the layout of the fragment state (tile or per-pixel lists, tile
+// size), so the backward must read the state with the forward's choice: a
+// backward asked for tuning -1 takes the recorded id rather than the
+// autotuner's cache (which may have changed in between), and one asked for
+// another explicit id is rejected.  At most kSavedRecords buffers are
+// remembered; the oldest record is dropped first.
+static std::mutex g_saved_mu;
+static std::map<const void*, std::pair<int, uint64_t>> g_saved_tuning;   // id, insertion stamp
+static uint64_t g_saved_stamp = 0;
+constexpr size_t kSavedRecords = 4096;
+
+static void record_saved_tuning(const void* saved, int tid) {
+    if (!saved) return;
+    std::lock_guard<std::mutex> lk(g_saved_mu);
+    g_saved_tuning[saved] = {tid, ++g_saved_stamp};
+    if (g_saved_tuning.size() > kSavedRecords) {
+        auto oldest = g_saved_tuning.begin();
+        for (auto it = g_saved_tuning.begin(); it != g_saved_tuning.end(); ++it)
+            if (it->second.second < oldest->second.second) oldest = it;
+        g_saved_tuning.erase(oldest);
+    }
+}
+
+static int saved_tuning(const void* saved) {
+    if (!saved) return -1;
+    std::lock_guard<std::mutex> lk(g_saved_mu);
+    auto it = g_saved_tuning.find(saved);
+    return it == g_saved_tuning.end() ? -1 : it->second.first;
 }
 
 // ------------------------------------------------- the fragment build
@@ -598,6 +636,12 @@ static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     if (!image || !t_final || !aligned(image, 16) || !aligned(t_final, 4)) return INPC_EINVAL;
     if (blend_weight && !aligned(blend_weight, 4)) return INPC_EINVAL;
     if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
+    {
+        const Layout L = make_layout(pb);
+        if (saved_bytes < L.saved_bytes || ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
+        if (pb.n_pixels > 0 && (!saved || !ws)) return INPC_EINVAL;
+    }
+    record_saved_tuning(saved, tid);
     return forward(pb, tid, xyz, feat, opa, tau, image, t_final, blend_weight, saved, saved_bytes, ws,
                    ws_bytes, static_cast<hipStream_t>(stream));
 }
@@ -699,7 +743,10 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     Problem pb;
     rc = make_problem(views, n_views, n_points, F, fdt, mode, 0, pb, avp);
     if (rc) return rc;
-    const int tid = resolve_tuning(treq, pb);
+    // The state must be read with the tuning of the forward that wrote it.
+    const int rec = saved_tuning(saved);
+    if (treq >= 0 && rec >= 0 && rec != treq) return INPC_EINVAL;
+    const int tid = treq >= 0 ? treq : (rec >= 0 ? rec : resolve_tuning(-1, pb));
     if (bwd_shape_of(tid, mode) != 0) {
         rc = make_problem(views, n_views, n_points, F, fdt, mode, bwd_shape_of(tid, mode), pb, avp);
         if (rc) return rc;
@@ -1036,6 +1083,11 @@ int inpc_state_info(const inpc_view_t* views, int32_t n_views, int64_t n_points,
 }
 
 int inpc_tuning_count(void) { return kNumTunings; }
+
+int inpc_saved_tuning(const void* saved) {
+    const int id = saved_tuning(saved);
+    return id >= 0 ? id : INPC_EINVAL;
+}
 
 const char* inpc_tuning_name(int32_t id) {
     if (id < 0 || id >= kNumTunings) return "";

@@ -303,8 +303,9 @@ void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView
                        rec, views, n_views, n_vp, chunk_cnt, pkey, pid);
 }
 
-// Tile entries: one (tile, view point) pair per distinct 16x16 tile that the
-// point's splats touch, written in the order of the depth-sorted points
+// Tile entries: one (tile, view point) pair per distinct square tile of
+// 2^lg pixels a side (8x8 by default, 16x16 as a tuning) that the point's
+// splats touch, written in the order of the depth-sorted points
 // (tiles of one point in ascending corner order of first appearance).
 __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,

@@ -190,3 +190,59 @@ def test_sampling_validation():
                                 None) == -1     # root size must be positive
     assert L.inpc_update_probabilities(FAKE, FAKE, 10, 1000, 0.9968, FAKE, FAKE, FAKE, need.value - 1,
                                        None) == -2
+
+
+def _gpu_visible() -> bool:
+    import torch
+    return torch.cuda.is_available()
+
+
+# The forward below passes validation with pointers that are never valid device
+# memory; without a GPU every HIP call fails before anything runs.  Where a GPU
+# is visible it is skipped (tests/test_gpu_parity.py covers the same on real
+# buffers).
+@pytest.mark.skipif(_gpu_visible(), reason="fake pointers may only reach the launch path without a GPU")
+def test_backward_uses_the_tuning_of_its_forward(tmp_path):
+    L = pr.lib()
+    c = pr.c_camera(cam())
+    n, F = 100, 4
+    fws, sv, bws = pr.plain_sizes(n, cam(), F, 0, 0)
+    saved = FAKE + (1 << 24)
+    st = pr.c_settings(1e-4, 0, 7)
+    rc = L.inpc_rasterize_fwd(FAKE, FAKE, 0, FAKE, n, F, ctypes.byref(c), ctypes.byref(st), FAKE, FAKE, None,
+                              saved, sv, FAKE, fws, None)
+    assert rc == -5                          # no device: nothing ran, but the arguments were accepted
+    assert L.inpc_saved_tuning(saved) == 7
+    assert L.inpc_saved_tuning(None) == -1 and L.inpc_saved_tuning(saved + 256) == -1
+    # the autotuner's cache changes between forward and backward: the bucket
+    # key is the device, view count, ceil(log2) of the view points and of the
+    # pixels, F and the feature type
+    import json
+    views = pr.make_views([cam()], [0], [n])
+    lg = lambda x: (int(x) - 1).bit_length()
+    bucket = f"gfx950|V1|N{lg(n)}|P{lg(64 * 48)}|F{F}|T0"
+    cache = tmp_path / "tune.json"
+    cache.write_text(json.dumps({bucket: 3}))
+    assert L.inpc_autotune_load(str(cache).encode()) >= 0
+    assert L.inpc_tuning_for(views, 1, n, F, 0) == 3
+
+    def bwd(tid):
+        s2 = pr.c_settings(1e-4, 0, tid)
+        return L.inpc_rasterize_bwd(FAKE, FAKE, 0, FAKE, n, F, ctypes.byref(c), ctypes.byref(s2), saved, sv,
+                                    FAKE, None, FAKE, FAKE, None, FAKE, bws, None)
+    assert bwd(3) == -1          # an explicit id other than the forward's is rejected
+    assert bwd(0) == -1
+    assert bwd(7) == -5          # the forward's id is accepted (then fails for want of a device)
+    assert bwd(-1) == -5         # -1 is accepted (it takes the recorded id, not the cache's 3)
+    # a state no forward recorded falls back to the cache
+    s3 = pr.c_settings(1e-4, 0, -1)
+    assert L.inpc_rasterize_bwd(FAKE, FAKE, 0, FAKE, n, F, ctypes.byref(c), ctypes.byref(s3), saved + 512, sv,
+                                FAKE, None, FAKE, FAKE, None, FAKE, bws, None) == -5
+    cache.write_text(json.dumps({bucket: 0}))
+    L.inpc_autotune_load(str(cache).encode())
+
+
+def test_negative_zero_near_plane_is_accepted():
+    d = cam().as_dict()
+    d["near"] = -0.0
+    assert _call_sizes(c=d) == 0

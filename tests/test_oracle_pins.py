@@ -741,3 +741,92 @@ def test_probability_update_eq2_eq3():
     # leaf 0: max(0.5, 0.75) and max(0.25, 0.75 - 0.125); leaf 1 and 3 decay; leaf 2: max(0.125, 0.5), max(0.25, 0)
     assert p.tolist() == [0.75, 0.25, 0.5, 0.0625]
     assert q.tolist() == [0.625, 0.25, 0.25, 0.5]
+
+
+# ---- re-sampling predicate (Appendix A.4) and uniform placement in the leaf (Section 3.2)
+def _wide_cam(R=None, t=None):
+    """W = 64, H = 32 (W != H), f = 32, principal point (32, 16): u = 32 x/z + 32, v = 32 y/z + 16."""
+    return workloads.Camera(R=np.eye(3, dtype=np.float32) if R is None else np.asarray(R, np.float32),
+                            t=np.zeros(3, np.float32) if t is None else np.asarray(t, np.float32),
+                            fx=32.0, fy=32.0, cx=32.0, cy=16.0, width=64, height=32, near=0.01, far=100.0)
+
+
+def test_point_visible_hand_cases():
+    """A sample counts as inside iff near < z < far, 0 <= u < W and 0 <= v < H
+    (every u, v below is exact in float32)."""
+    from oracle import sampling as S
+    f32 = np.float32
+    near_up = float(np.nextafter(f32(0.01), f32(1)))
+    far_down = float(np.nextafter(f32(100), f32(0)))
+    cases = [
+        ((0.96875, 0.0, 1.0), True),      # u = 63 = W - 1
+        ((1.0, 0.0, 1.0), False),         # u = 64 = W: the right border is outside
+        ((-1.0, 0.0, 1.0), True),         # u = 0: the left border is inside
+        ((-1.03125, 0.0, 1.0), False),    # u = -1
+        ((0.0, 0.46875, 1.0), True),      # v = 31 = H - 1
+        ((0.0, 0.5, 1.0), False),         # v = 32 = H (still < W: catches W and H swapped)
+        ((0.0, -0.5, 1.0), True),         # v = 0
+        ((0.25, -0.1875, 1.0), True),     # u = 40 >= H, v = 10 (catches W and H swapped)
+        ((0.0, 0.75, 1.0), False),        # v = 40: H < v < W
+        ((0.0, 0.0, 0.01), False),        # z = near exactly
+        ((0.0, 0.0, near_up), True),      # just past the near plane
+        ((0.0, 0.0, 100.0), False),       # z = far exactly
+        ((0.0, 0.0, far_down), True),     # just inside the far plane
+        ((1.0, 0.0, -2.0), False),        # behind the camera although u = 16, v = 16 lie in the image
+        ((0.0, 0.0, -1.0), False),
+        ((float("nan"), 0.0, 1.0), False),
+        ((0.0, 0.0, 0.0), False),         # at the camera centre
+    ]
+    xyz = np.array([c for c, _ in cases], np.float32)
+    got = S.point_visible(xyz, _wide_cam())
+    assert got.tolist() == [v for _, v in cases]
+    # rotation and translation enter as x_c = R x + t (a transposed R or a dropped t fails)
+    R = [[0, 0, 1], [0, 1, 0], [-1, 0, 0]]        # x_c = z, z_c = -x
+    pts = np.array([[-1.0, 0.0, 0.5], [1.0, 0.0, 0.5], [0.0, 0.0, 0.5]], np.float32)
+    assert S.point_visible(pts, _wide_cam(R)).tolist() == [True, False, False]
+    assert S.point_visible(pts, _wide_cam(R, t=[0.0, 0.0, 1.0])).tolist() == [True, False, True]
+
+
+def test_unit24_takes_the_top_24_bits():
+    from oracle import sampling as S
+    words = np.array([1 << 63, (1 << 64) - 1, (1 << 40) - 1, 1 << 40, 0, 0xABCDEF0000000000,
+                      (0x123456 << 40) | 0xFFFFFFFFFF], np.uint64)
+    got = S.unit24(words)
+    assert got.dtype == np.float32
+    assert got.tolist() == [0.5, 1.0 - 2.0 ** -24, 0.0, 2.0 ** -24, 0.0, 0xABCDEF / 2.0 ** 24,
+                            0x123456 / 2.0 ** 24]
+    rnd = S.random_block(np.arange(50_000), 0, S.STREAM_VIEW, (11, 12))[:, 1]
+    u = S.unit24(rnd).astype(np.float64)
+    assert np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))          # on the 2^-24 grid
+    assert u.min() >= 0.0 and u.max() < 1.0 and u.min() < 1e-3 and u.max() > 1 - 1e-3
+
+
+def test_place_hand_case():
+    from oracle import sampling as S
+    centre = np.array([[1.0, 2.0, 3.0]], np.float32)
+    level = np.array([1], np.int32)                      # edge = 4 * 2^-1 = 2
+    frac = np.array([[0.0, 0.5, 0.75]], np.float32)
+    assert S._place(centre, level, 4.0, np.array([0]), frac).tolist() == [[0.0, 2.0, 3.5]]
+
+
+def test_view_samples_are_uniform_inside_the_leaf():
+    """Positions fill the leaf uniformly and independently per axis (KS test,
+    mean, both halves, no correlation between axes)."""
+    from scipy.stats import kstest
+    from oracle import sampling as S
+    centre = np.array([[0.0, 0.0, 4.0]], np.float32)
+    level = np.array([0], np.int32)
+    cam = workloads.canonical_camera(64, 64)
+    n = 60_000
+    xyz, leaf, _ = S.sample_view(centre, level, np.array([1.0], np.float32), 1.0, 0.5, 1e-8, cam, n, (21, 22), 0)
+    assert np.all(leaf == 0)
+    frac = (xyz.astype(np.float64) - centre[0]) / 1.0 + 0.5
+    sd = 1.0 / np.sqrt(12.0 * n)
+    for a in range(3):
+        f = frac[:, a]
+        assert kstest(f, "uniform").pvalue > 1e-4
+        assert abs(f.mean() - 0.5) < 5 * sd
+        assert abs(np.mean(f < 0.5) - 0.5) < 5 * 0.5 / np.sqrt(n)
+        assert f.min() >= 0.0 and f.max() < 1.0
+    c = np.corrcoef(frac.T)
+    assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 5 / np.sqrt(n))
