@@ -232,11 +232,13 @@ static size_t max_counts_words(const Problem& pb) {
     return w;
 }
 
-static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f) {
+// with_tk: room for the T_k of every blended splat; only a state the
+// backward reads needs it (the RECOMPUTE forward keeps none).
+static void carve_frag(Carver& c, const Problem& pb, FragOffsets& f, bool with_tk = true) {
     f.rec = c.take((size_t)pb.n_vp * sizeof(PointRec));
     f.ids = c.take((size_t)4 * pb.n_vp * 4);
     f.range = c.take((size_t)pb.n_pixels * sizeof(uint2));
-    f.tk = c.take((size_t)4 * pb.n_vp * 16);   // at most 4 entries per point, 4 floats each
+    f.tk = with_tk ? c.take((size_t)4 * pb.n_vp * 16) : 0;   // at most 4 entries per point, 4 floats each
     f.payload = c.take((size_t)pb.n_vp * payload_stride(pb.F, pb.fdt));
     f.perm = c.take((size_t)pb.n_pixels * 4);   // tiles <= pixels
 }
@@ -266,7 +268,7 @@ static Layout make_layout(const Problem& pb) {
     L.s_scalars = s.take(256);
     if (pb.mode == INPC_SAVE) carve_frag(s, pb, L.saved_frag);
     carve_build(f, pb, L.fwd_build);
-    if (pb.mode == INPC_RECOMPUTE) carve_frag(f, pb, L.fwd_frag);
+    if (pb.mode == INPC_RECOMPUTE) carve_frag(f, pb, L.fwd_frag, false);
     L.b_views = b.take(pb.views.size() * sizeof(GpuView));
     L.b_frec = b.take((size_t)4 * pb.n_vp * sizeof(float2));
     if (pb.mode == INPC_RECOMPUTE) {

@@ -4,10 +4,11 @@ benchmark times (default tuning):
 * 8M points at 1920x1080, F=16 float32, forward + backward through
   torch.autograd.Function: the whole sorted splat list bit-exact, every image
   element and gradient against the oracle, central differences on 64 points;
-* the 16-view batched bfloat16 workload as one graph replay, three views
+* the 16-view batched bfloat16 workload as one graph replay, every view
   checked completely against the oracle;
-* 32M points (clusters plus a far background shell), one 1080p pose, bfloat16
-  features, forward only.
+* 32M points (clusters plus a far background shell), 8 poses at 1080p,
+  bfloat16 features, forward only: each pose as a plain call, the 8 poses as
+  one batched call over aliased views, and the far = 10^3 variant.
 
 The first also checks the per-point blend weights of every point.
 """
@@ -54,7 +55,11 @@ def test_config3_full_autograd_with_fd():
     H.check_blend_weight(bw.cpu().numpy(), L, s.opa, n_gpu)
 
 
-def test_config4_batched_graph_sampled_views():
+def test_config4_batched_graph_all_views():
+    """All 16 views of the timed graph replay: splat lists bit-exact, image and
+    transmittance within 1e-5 of the oracle on the bfloat16-rounded features,
+    within 1e-2 of the oracle on the unrounded float32 features, gradients
+    against the oracle's adjoint."""
     b = workloads.config4()
     views = pr.make_views(b.cams, b.point_offset, b.point_count)
     g = np.concatenate([gi.reshape(-1, b.F) for gi in b.g_imgs])
@@ -66,46 +71,111 @@ def test_config4_batched_graph_sampled_views():
     torch.cuda.synchronize()
     keys, ids, nb = pr.debug_fragments(step.state())
     img = step.image.cpu().numpy()
+    tf = step.t_final.cpu().numpy()
     gf, go = step.grad_feat.cpu().numpy(), step.grad_opa.cpu().numpy()
     P_v = [c.width * c.height for c in b.cams]
     pix_off = np.concatenate([[0], np.cumsum(P_v)]).astype(np.int64)
     vp_off = np.concatenate([[0], np.cumsum(b.point_count)]).astype(np.int64)
     pix = keys >> np.uint64(32)
+    vbound = np.searchsorted(pix, pix_off.astype(np.uint64))     # keys are sorted by pixel
     fbits = H.bf16_bits(b.feat)
-    for v in (0, int(np.argmax(b.point_count)), len(b.cams) - 1):
+    worst = dict(img_rounded=0.0, img_unrounded=0.0, t_final=0.0)
+    for v in range(len(b.cams)):
         sl = slice(b.point_offset[v], b.point_offset[v] + b.point_count[v])
         L = oracle.fragments(b.xyz[sl], b.cams[v])
         lo, hi = int(pix_off[v]), int(pix_off[v + 1])
-        sel = (pix >= lo) & (pix < hi)
-        assert np.array_equal(keys[sel], L.keys(lo))
-        assert np.array_equal(ids[sel].astype(np.int64) - 4 * int(vp_off[v]), L.ids.astype(np.int64))
+        a, e = int(vbound[v]), int(vbound[v + 1])
+        assert np.array_equal(keys[a:e], L.keys(lo))
+        assert np.array_equal(ids[a:e].astype(np.int64) - 4 * int(vp_off[v]), L.ids.astype(np.int64))
         n_gpu = nb[lo:hi].astype(np.int32)
         ref_t = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, want_t_after=True)
-        H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
+        amb = H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
         ref = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, n_override=n_gpu)
-        e = H.rel_err(img[lo:hi], ref["image"])
-        assert e.max() <= H.REL_TOL, e.max()
+        e_img = H.rel_err(img[lo:hi], ref["image"]).max()
+        e_t = H.rel_err(tf[lo:hi], ref["t_final"]).max()
+        assert e_img <= H.REL_TOL and e_t <= H.REL_TOL, (v, e_img, e_t)
         unr = oracle.blend_forward(L, b.opa[sl], b.feat[sl], 1e-4, n_override=n_gpu)
-        assert np.abs(img[lo:hi] - unr["image"]).max() <= H.BF16_ABS_TOL
+        e_unr = float(np.abs(img[lo:hi] - unr["image"]).max())
+        assert e_unr <= H.BF16_ABS_TOL, (v, e_unr)
         rb = oracle.blend_backward(L, b.opa[sl], fbits[sl], n_gpu, g[lo:hi])
         H.check_grads(gf[vp_off[v]:vp_off[v + 1]], go[vp_off[v]:vp_off[v + 1]], rb)
-        H.say(f"    view {v}: {b.cams[v].width}x{b.cams[v].height} N={b.point_count[v]} M={L.m} ok")
+        worst = dict(img_rounded=max(worst["img_rounded"], e_img), img_unrounded=max(worst["img_unrounded"], e_unr),
+                     t_final=max(worst["t_final"], e_t))
+        H.say(f"    view {v}: {b.cams[v].width}x{b.cams[v].height} N={b.point_count[v]} M={L.m} "
+              f"ambiguous={amb} ok")
+        del L, ref_t, ref, unr, rb
+    H.say(f"    worst over 16 views: {worst}")
 
 
-def test_config5_one_pose_bf16_forward():
-    b = workloads.config5()
-    cam = b.cams[3]
+@pytest.fixture(scope="module")
+def config5_scene():
+    return workloads.config5()
+
+
+def _check_pose(L, opa, feat, fbits, img, tf, n_gpu, label):
+    ref_t = oracle.blend_forward(L, opa, fbits, 1e-4, want_t_after=True)
+    amb = H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
+    del ref_t
+    ref = oracle.blend_forward(L, opa, fbits, 1e-4, n_override=n_gpu)
+    e = H.rel_err(img, ref["image"]).max()
+    et = H.rel_err(tf, ref["t_final"]).max()
+    assert e <= H.REL_TOL and et <= H.REL_TOL, (label, e, et)
+    del ref
+    unr = oracle.blend_forward(L, opa, feat, 1e-4, n_override=n_gpu)
+    eu = float(np.abs(img - unr["image"]).max())
+    assert eu <= H.BF16_ABS_TOL, (label, eu)
+    H.say(f"    {label}: M={L.m} blended={int(n_gpu.sum())} ambiguous={amb} image err {e:.2e} "
+          f"t_final err {et:.2e} unrounded-feature err {eu:.2e}")
+
+
+def test_config5_all_poses_plain_and_aliased_batched(config5_scene):
+    """32M points (clusters plus a background shell), 8 poses on a circle,
+    bfloat16 features, forward only: every pose as a plain call, and the 8
+    poses as one batched call whose views all alias the same points."""
+    b = config5_scene
+    n = b.xyz.shape[0]
+    x, o = H.to_dev(b.xyz), H.to_dev(b.opa)
+    f = H.to_dev(b.feat).to(torch.bfloat16)
+    fbits = H.bf16_bits(b.feat)
+    views = pr.make_views(b.cams, b.point_offset, b.point_count)
+    img_b, tf_b, st_b = pr.rasterize_forward_batched(x, f, o, views, 1e-4, "save", keep_workspace=True)
+    keys_b, ids_b, nb_b = pr.debug_fragments(st_b)
+    img_b, tf_b = img_b.cpu().numpy(), tf_b.cpu().numpy()
+    del st_b
+    torch.cuda.empty_cache()
+    P = b.cams[0].width * b.cams[0].height
+    vbound = np.searchsorted(keys_b >> np.uint64(32), (np.arange(len(b.cams) + 1) * P).astype(np.uint64))
+    H.say(f"  config 5: N={n}, 8 aliased views, {keys_b.shape[0]} splats in the batched call")
+    for v, cam in enumerate(b.cams):
+        img, tf, st = pr.rasterize_forward(x, f, o, cam, 1e-4, keep_workspace=True)
+        keys, ids, nb = pr.debug_fragments(st)
+        img, tf = img.reshape(-1, 16).cpu().numpy(), tf.reshape(-1).cpu().numpy()
+        del st
+        L = oracle.fragments(b.xyz, cam)
+        assert np.array_equal(keys, L.keys()) and np.array_equal(ids, L.ids), v
+        a, e = int(vbound[v]), int(vbound[v + 1])
+        assert np.array_equal(keys_b[a:e], L.keys(v * P)), v
+        assert np.array_equal(ids_b[a:e].astype(np.int64) - 4 * v * n, L.ids.astype(np.int64)), v
+        n_gpu = nb.astype(np.int32)
+        assert np.array_equal(nb_b[v * P:(v + 1) * P], nb), v
+        _check_pose(L, b.opa, b.feat, fbits, img, tf, n_gpu, f"pose {v} plain")
+        # the batched call blends the same lists with the same arithmetic
+        assert np.array_equal(img_b[v * P:(v + 1) * P], img) and np.array_equal(tf_b[v * P:(v + 1) * P], tf), v
+        H.say(f"    pose {v} batched: lists and blend counts equal the oracle's, image equal to the plain call")
+        del keys, ids, nb, L
+
+
+def test_config5_far_plane_1000(config5_scene):
+    """The far = 10^3 variant: the background shell (radius 50-200) is no longer culled."""
+    import copy
+    b = config5_scene
+    cam = copy.deepcopy(b.cams[0])
+    cam.far = 1000.0
     x, o = H.to_dev(b.xyz), H.to_dev(b.opa)
     f = H.to_dev(b.feat).to(torch.bfloat16)
     img, tf, st = pr.rasterize_forward(x, f, o, cam, 1e-4, keep_workspace=True)
     keys, ids, nb = pr.debug_fragments(st)
     L = oracle.fragments(b.xyz, cam)
     assert np.array_equal(keys, L.keys()) and np.array_equal(ids, L.ids)
-    n_gpu = nb.astype(np.int32)
-    fbits = H.bf16_bits(b.feat)
-    ref_t = oracle.blend_forward(L, b.opa, fbits, 1e-4, want_t_after=True)
-    amb = H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
-    ref = oracle.blend_forward(L, b.opa, fbits, 1e-4, n_override=n_gpu)
-    e = H.rel_err(img.reshape(-1, 16).cpu().numpy(), ref["image"])
-    H.say(f"    config 5 pose 3: M={L.m} blended={int(n_gpu.sum())} ambiguous={amb} image err {e.max():.2e}")
-    assert e.max() <= H.REL_TOL
+    _check_pose(L, b.opa, b.feat, H.bf16_bits(b.feat), img.reshape(-1, 16).cpu().numpy(),
+                tf.reshape(-1).cpu().numpy(), nb.astype(np.int32), "pose 0, far 1000")
