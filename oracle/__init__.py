@@ -24,7 +24,9 @@ from typing import Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liborc.so")
+# INPC_ORACLE_LIB selects another build of oracle.c (the sanitizer test loads
+# the AddressSanitizer/UBSan build through it)
+LIB_PATH = os.environ.get("INPC_ORACLE_LIB") or os.path.join(HERE, "liborc.so")
 
 
 class _Camera(ctypes.Structure):

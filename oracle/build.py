@@ -14,14 +14,17 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
 
 
-def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm"]
+def build(verbose: bool = False, lib_path: str = None, opt_flags=("-O2",)) -> str:
+    """Builds ``lib_path`` (default the in-tree liborc.so); ``opt_flags``
+    replace -O2 (the sanitizer test builds a variant)."""
+    out = lib_path or LIB
+    cmd = ["gcc"] + list(opt_flags) + ["-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                                       "-fPIC", "-shared", "-Wall", "-Wextra", "-o", out + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -19,8 +19,14 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 6) -> str:
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 6, objdir: str = None, lib_path: str = None,
+          extra_flags=(), link_flags=()) -> str:
+    """Compiles every source and links the library (``lib_path``, default
+    the in-tree libinpc_raster.so); ``extra_flags`` / ``link_flags`` are added
+    to the compile / link lines (the sanitizer test builds a variant)."""
+    objdir = objdir or os.path.join(HERE, "_build")
+    lib_path = lib_path or LIB
+    extra = list(extra_flags)
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
@@ -28,7 +34,7 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
@@ -38,12 +44,12 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + list(link_flags) + ["-o", lib_path + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib_path + ".tmp", lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
