@@ -28,7 +28,9 @@ from typing import List, Optional, Sequence
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libinpc_raster.so")
+# INPC_RASTER_LIB selects another build of the same sources (the sanitizer
+# test loads the build whose host code carries AddressSanitizer/UBSan)
+LIB_PATH = os.environ.get("INPC_RASTER_LIB") or os.path.join(HERE, "libinpc_raster.so")
 
 INPC_F32, INPC_BF16 = 0, 1
 INPC_SAVE, INPC_RECOMPUTE = 0, 1
