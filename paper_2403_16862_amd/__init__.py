@@ -220,9 +220,9 @@ def _check_points(xyz: torch.Tensor, feat: torch.Tensor, opa: torch.Tensor, n_at
 
 
 # ------------------------------------------------------------------ plain calls
-def plain_sizes(n: int, cam, F: int, fdt: int, mode: int):
+def plain_sizes(n: int, cam, F: int, fdt: int, mode: int, ccam: Optional[CCamera] = None):
     a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
-    cc = c_camera(cam)
+    cc = ccam if ccam is not None else c_camera(cam)
     _check(lib().inpc_plain_sizes(int(n), ctypes.byref(cc), int(F), int(fdt), int(mode),
                                   ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "inpc_plain_sizes")
     return a.value, b.value, c.value
@@ -248,6 +248,7 @@ class ForwardState:
     n_points: int
     F: int
     fdt: int
+    plain: bool = False   # made by the plain one-view entry point (inpc_rasterize_fwd)
 
 
 def rasterize_forward(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save",
@@ -262,7 +263,7 @@ def rasterize_forward(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save
     cams = [cam]
     views, P = c_views(cams, [0], [xyz.shape[0]])
     return _forward(xyz, feat, opa, views, 1, t_threshold, mode, tuning_id, keep_workspace,
-                    (views[0].cam.height, views[0].cam.width), blend_weight)
+                    (views[0].cam.height, views[0].cam.width), blend_weight, plain=True)
 
 
 def rasterize_forward_batched(xyz, feat, opa, views, t_threshold: float = 1e-4, mode="save",
@@ -288,12 +289,18 @@ def _check_blend_weight(bw, views, n_views, dev):
 
 
 def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_workspace, img_hw,
-             blend_weight=None, flags: int = 0):
+             blend_weight=None, flags: int = 0, plain: bool = False):
+    """plain: one camera over all points (views[0]), through the plain entry
+    points inpc_rasterize_fwd / inpc_rasterize_bwd; else the batched ones."""
     m = _mode(mode)
     fdt = _fdt(feat)
     F = int(feat.shape[1])
     N = int(xyz.shape[0])
-    fws, sv, _ = batched_sizes(views, n_views, N, F, fdt, m)
+    if plain:
+        assert n_views == 1 and flags == 0 and views[0].point_offset == 0 and views[0].point_count == N
+        fws, sv, _ = plain_sizes(N, None, F, fdt, m, ccam=views[0].cam)
+    else:
+        fws, sv, _ = batched_sizes(views, n_views, N, F, fdt, m)
     dev = xyz.device
     saved = _buffer(sv, dev)
     ws = _buffer(fws, dev)
@@ -306,14 +313,20 @@ def _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id, keep_
         t_final = torch.empty((P,), dtype=torch.float32, device=dev)
     st = c_settings(t_threshold, m, tuning_id, flags)
     _check_blend_weight(blend_weight, views, n_views, dev)
-    _check(lib().inpc_rasterize_fwd_batched(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, views, n_views,
-                                            ctypes.byref(st), _ptr(image), _ptr(t_final),
-                                            _ptr(blend_weight), _ptr(saved), saved.numel(), _ptr(ws),
-                                            ws.numel(), _stream()),
-           "inpc_rasterize_fwd")
+    if plain:
+        _check(lib().inpc_rasterize_fwd(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, ctypes.byref(views[0].cam),
+                                        ctypes.byref(st), _ptr(image), _ptr(t_final), _ptr(blend_weight),
+                                        _ptr(saved), saved.numel(), _ptr(ws), ws.numel(), _stream()),
+               "inpc_rasterize_fwd")
+    else:
+        _check(lib().inpc_rasterize_fwd_batched(_ptr(xyz), _ptr(feat), fdt, _ptr(opa), N, F, views, n_views,
+                                                ctypes.byref(st), _ptr(image), _ptr(t_final),
+                                                _ptr(blend_weight), _ptr(saved), saved.numel(), _ptr(ws),
+                                                ws.numel(), _stream()),
+               "inpc_rasterize_fwd_batched")
     # the backward reads the state with the tuning this forward used
     st.tuning_id = _check(lib().inpc_saved_tuning(_ptr(saved)), "inpc_saved_tuning")
-    state = ForwardState(saved, ws if keep_workspace else None, st, views, n_views, N, F, fdt)
+    state = ForwardState(saved, ws if keep_workspace else None, st, views, n_views, N, F, fdt, plain)
     return image, t_final, state
 
 
@@ -324,27 +337,40 @@ def rasterize_backward(xyz, feat, opa, state: ForwardState, g_img, g_t=None, ble
     g_img = g_img.contiguous().float()
     g_t = None if g_t is None else g_t.contiguous().float()
     nvp = sum(int(state.views[i].point_count) for i in range(state.n_views))
-    _, _, bws = batched_sizes(state.views, state.n_views, state.n_points, state.F, state.fdt,
-                              state.settings.mode)
+    if state.plain:
+        _, _, bws = plain_sizes(state.n_points, None, state.F, state.fdt, state.settings.mode,
+                                ccam=state.views[0].cam)
+    else:
+        _, _, bws = batched_sizes(state.views, state.n_views, state.n_points, state.F, state.fdt,
+                                  state.settings.mode)
     dev = xyz.device
     ws = _buffer(bws, dev)
     gf = torch.empty((nvp, state.F), dtype=torch.float32, device=dev)
     go = torch.empty((nvp,), dtype=torch.float32, device=dev)
     _check_blend_weight(blend_weight, state.views, state.n_views, dev)
-    _check(lib().inpc_rasterize_bwd_batched(_ptr(xyz), _ptr(feat), state.fdt, _ptr(opa), state.n_points,
-                                            state.F, state.views, state.n_views,
-                                            ctypes.byref(state.settings), _ptr(state.saved),
-                                            state.saved.numel(), _ptr(g_img), _ptr(g_t), _ptr(gf),
-                                            _ptr(go), _ptr(blend_weight), _ptr(ws), ws.numel(), _stream()),
-           "inpc_rasterize_bwd")
+    if state.plain:
+        _check(lib().inpc_rasterize_bwd(_ptr(xyz), _ptr(feat), state.fdt, _ptr(opa), state.n_points, state.F,
+                                        ctypes.byref(state.views[0].cam), ctypes.byref(state.settings),
+                                        _ptr(state.saved), state.saved.numel(), _ptr(g_img), _ptr(g_t),
+                                        _ptr(gf), _ptr(go), _ptr(blend_weight), _ptr(ws), ws.numel(),
+                                        _stream()),
+               "inpc_rasterize_bwd")
+    else:
+        _check(lib().inpc_rasterize_bwd_batched(_ptr(xyz), _ptr(feat), state.fdt, _ptr(opa), state.n_points,
+                                                state.F, state.views, state.n_views,
+                                                ctypes.byref(state.settings), _ptr(state.saved),
+                                                state.saved.numel(), _ptr(g_img), _ptr(g_t), _ptr(gf),
+                                                _ptr(go), _ptr(blend_weight), _ptr(ws), ws.numel(), _stream()),
+               "inpc_rasterize_bwd_batched")
     return gf, go
 
 
 class _Rasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, xyz, feat, opa, views, n_views, img_hw, t_threshold, mode, tuning_id, fold, flags):
+    def forward(ctx, xyz, feat, opa, views, n_views, img_hw, t_threshold, mode, tuning_id, fold, flags,
+                plain=False):
         image, t_final, state = _forward(xyz, feat, opa, views, n_views, t_threshold, mode, tuning_id,
-                                         False, img_hw, None, flags)
+                                         False, img_hw, None, flags, plain)
         ctx.state = state
         ctx.fold = fold
         ctx.set_materialize_grads(False)
@@ -356,14 +382,14 @@ class _Rasterize(torch.autograd.Function):
         xyz, feat, opa = ctx.saved_tensors
         st = ctx.state
         if g_img is None and g_t is None:
-            return (None,) * 11
+            return (None,) * 12
         if g_img is None:
             P = sum(st.views[i].cam.width * st.views[i].cam.height for i in range(st.n_views))
             g_img = torch.zeros((P, st.F), dtype=torch.float32, device=xyz.device)
         gf, go = rasterize_backward(xyz, feat, opa, st, g_img, g_t)
         if ctx.fold:
             gf, go = sum_view_grads(st.views, st.n_views, st.n_points, gf, go)
-        return None, gf, go, None, None, None, None, None, None, None, None
+        return None, gf, go, None, None, None, None, None, None, None, None, None
 
 
 def rasterize(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save", tuning_id: int = -1):
@@ -372,7 +398,7 @@ def rasterize(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save", tunin
     xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
     views, _ = c_views([cam], [0], [xyz.shape[0]])
     hw = (views[0].cam.height, views[0].cam.width)
-    return _Rasterize.apply(xyz, feat, opa, views, 1, hw, t_threshold, mode, tuning_id, False, 0)
+    return _Rasterize.apply(xyz, feat, opa, views, 1, hw, t_threshold, mode, tuning_id, False, 0, True)
 
 
 def make_views(cams: Sequence, point_offsets: Sequence[int], point_counts: Sequence[int]):
