@@ -67,6 +67,7 @@ extern "C" {
 #define INPC_EUNSUPPORTED (-3) /* F outside 1..64, image side outside 1..16383 */
 #define INPC_EOVERFLOW (-4)    /* too many points or pixels for the index widths */
 #define INPC_EHIP (-5)         /* a HIP runtime call failed; see inpc_last_hip_error() */
+#define INPC_ESCRATCH (-6)     /* needs more than INPC_NOALLOC_SCRATCH_BYTES (no-allocation call) */
 
 typedef enum { INPC_F32 = 0, INPC_BF16 = 1 } inpc_dtype_t;
 
@@ -154,6 +155,37 @@ int inpc_rasterize_bwd(const float *xyz, const void *feat, int32_t feat_dtype,
                        const void *saved, size_t saved_bytes, const float *grad_image,
                        const float *grad_t_final, float *grad_feat, float *grad_opacity,
                        float *blend_weight, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------- no-allocation forward */
+
+/* Bytes of the fixed device scratch behind inpc_rasterize_fwd_noalloc: one
+ * array of this size per GPU the library runs on, held until the process
+ * ends. */
+#define INPC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of inpc_rasterize_fwd with its state and workspace taken from a
+ * file-scope device array of INPC_NOALLOC_SCRATCH_BYTES instead of caller
+ * buffers.  Nothing is allocated, by the library or by any routine it calls.
+ * Arguments and outputs as for inpc_rasterize_fwd; no state is kept for a
+ * backward, so settings->mode must be INPC_RECOMPUTE (else INPC_EINVAL).
+ * The results equal those of inpc_rasterize_fwd with the same arguments.
+ * A problem whose recompute-mode state plus forward workspace
+ * (inpc_plain_sizes with mode INPC_RECOMPUTE; each part rounded up to 256
+ * bytes) exceeds INPC_NOALLOC_SCRATCH_BYTES is rejected with INPC_ESCRATCH
+ * before anything is enqueued (up to about 1.37M points fit at 1280x720 with
+ * F=8, 0.87M at 1920x1080 with F=16 float32, 1.19M with F=16 bfloat16).
+ * Every call on one GPU uses that GPU's one array, whose contents the
+ * previous call left there; every buffer that must start at a value is set
+ * by the call's own kernels.  Calls that overlap on one GPU (other streams,
+ * other threads) race on the array: serialise them.  The first call on each
+ * device looks up the array's device address (a runtime query, no
+ * allocation); make that first call outside graph capture. */
+int inpc_rasterize_fwd_noalloc(const float *xyz, const void *feat, int32_t feat_dtype,
+                               const float *opacity, int64_t n_points, int32_t F,
+                               const inpc_camera_t *cam_host, const inpc_settings_t *settings_host,
+                               float *image, float *t_final, float *blend_weight, void *stream);
 
 /* ---------------------------------------------------------- batched calls */
 

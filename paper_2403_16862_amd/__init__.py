@@ -34,7 +34,8 @@ LIB_PATH = os.environ.get("INPC_RASTER_LIB") or os.path.join(HERE, "libinpc_rast
 
 INPC_F32, INPC_BF16 = 0, 1
 INPC_SAVE, INPC_RECOMPUTE = 0, 1
-ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EUNSUPPORTED", -4: "EOVERFLOW", -5: "EHIP"}
+ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EUNSUPPORTED", -4: "EOVERFLOW", -5: "EHIP",
+          -6: "ESCRATCH"}
 
 
 class InpcError(RuntimeError):
@@ -81,6 +82,7 @@ def lib():
         "inpc_batched_sizes": [view_p, i32, i64, i32, i32, i32, szp, szp, szp],
         "inpc_rasterize_fwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, P, sz, P, sz, P],
         "inpc_rasterize_bwd": [P, P, i32, P, i64, i32, cam_p, set_p, P, sz, P, P, P, P, P, P, sz, P],
+        "inpc_rasterize_fwd_noalloc": [P, P, i32, P, i64, i32, cam_p, set_p, P, P, P, P],
         "inpc_rasterize_fwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, P, P, P, sz, P, sz,
                                        P],
         "inpc_rasterize_bwd_batched": [P, P, i32, P, i64, i32, view_p, i32, set_p, P, sz, P, P, P, P, P,
@@ -264,6 +266,28 @@ def rasterize_forward(xyz, feat, opa, cam, t_threshold: float = 1e-4, mode="save
     views, P = c_views(cams, [0], [xyz.shape[0]])
     return _forward(xyz, feat, opa, views, 1, t_threshold, mode, tuning_id, keep_workspace,
                     (views[0].cam.height, views[0].cam.width), blend_weight, plain=True)
+
+
+def rasterize_forward_noalloc(xyz, feat, opa, cam, t_threshold: float = 1e-4, tuning_id: int = -1,
+                              blend_weight=None):
+    """Forward of one view through inpc_rasterize_fwd_noalloc (state and
+    workspace in the library's fixed per-GPU scratch, no backward state);
+    returns (image [H,W,F], t_final [H,W]).  Only the outputs are allocated
+    here, by torch."""
+    _check_points(xyz, feat, opa)
+    xyz, feat, opa = xyz.contiguous(), feat.contiguous(), opa.contiguous()
+    cc = c_camera(cam)
+    F = int(feat.shape[1])
+    dev = xyz.device
+    image = torch.empty((cc.height, cc.width, F), dtype=torch.float32, device=dev)
+    t_final = torch.empty((cc.height, cc.width), dtype=torch.float32, device=dev)
+    views, _ = c_views([cam], [0], [xyz.shape[0]])
+    _check_blend_weight(blend_weight, views, 1, dev)
+    st = c_settings(t_threshold, INPC_RECOMPUTE, tuning_id)
+    _check(lib().inpc_rasterize_fwd_noalloc(_ptr(xyz), _ptr(feat), _fdt(feat), _ptr(opa), int(xyz.shape[0]), F,
+                                            ctypes.byref(cc), ctypes.byref(st), _ptr(image), _ptr(t_final),
+                                            _ptr(blend_weight), _stream()), "inpc_rasterize_fwd_noalloc")
+    return image, t_final
 
 
 def rasterize_forward_batched(xyz, feat, opa, views, t_threshold: float = 1e-4, mode="save",

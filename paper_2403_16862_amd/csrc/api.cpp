@@ -768,6 +768,36 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
 
 using namespace inpc;
 
+// ------------------------------------------------ no-allocation forward
+// The state and workspace of inpc_rasterize_fwd_noalloc: one array per GPU,
+// held until the process ends.  In host code the name ``scratch`` only stands
+// for the array; its device address on the current device comes from
+// hipGetSymbolAddress (looked up once per device and kept), and only that
+// address is handed to kernels.
+constexpr size_t kScratchBytes = INPC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+static int scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kScratchDevices) return INPC_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (reinterpret_cast<uintptr_t>(p) % 256) != 0) return INPC_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return INPC_OK;
+}
+
 extern "C" {
 
 int inpc_version(void) { return 1; }
@@ -780,6 +810,7 @@ const char* inpc_error_string(int code) {
         case INPC_EUNSUPPORTED: return "unsupported feature count or image size";
         case INPC_EOVERFLOW: return "too many points or pixels for the index widths";
         case INPC_EHIP: return "HIP runtime error";
+        case INPC_ESCRATCH: return "problem needs more than the fixed scratch of inpc_rasterize_fwd_noalloc";
         default: return "unknown error";
     }
 }
@@ -817,6 +848,25 @@ int inpc_rasterize_bwd(const float* xyz, const void* feat, int32_t fdt, const fl
     const inpc_view_t v = single_view(cam, n_points);
     return bwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, saved, saved_bytes, g_img, g_t,
                     grad_feat, grad_opa, blend_weight, ws, ws_bytes, stream);
+}
+
+int inpc_rasterize_fwd_noalloc(const float* xyz, const void* feat, int32_t fdt, const float* opa,
+                               int64_t n_points, int32_t F, const inpc_camera_t* cam,
+                               const inpc_settings_t* st, float* image, float* t_final, float* blend_weight,
+                               void* stream) {
+    if (!cam || !st) return INPC_EINVAL;
+    if (st->mode != INPC_RECOMPUTE) return INPC_EINVAL;
+    const inpc_view_t v = single_view(cam, n_points);
+    size_t fws = 0, sv = 0;
+    int rc = sizes_impl(&v, 1, n_points, F, fdt, INPC_RECOMPUTE, &fws, &sv, nullptr);
+    if (rc) return rc;
+    const size_t sv_room = (sv + 255) & ~(size_t)255;
+    if (sv_room > kScratchBytes || fws > kScratchBytes - sv_room) return INPC_ESCRATCH;
+    void* base = nullptr;
+    rc = scratch_of_current_device(&base);
+    if (rc) return rc;
+    return fwd_impl(xyz, feat, fdt, opa, n_points, F, &v, 1, st, image, t_final, blend_weight, base, sv,
+                    static_cast<unsigned char*>(base) + sv_room, fws, stream);
 }
 
 int inpc_rasterize_fwd_batched(const float* xyz, const void* feat, int32_t fdt, const float* opa,

@@ -33,8 +33,9 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_error_strings():
     L = pr.lib()
     assert L.inpc_version() >= 1
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.inpc_error_string(code)
+    assert L.inpc_error_string(-6) != L.inpc_error_string(-99)
 
 
 def test_tuning_table_is_listed():
@@ -246,3 +247,33 @@ def test_negative_zero_near_plane_is_accepted():
     d = cam().as_dict()
     d["near"] = -0.0
     assert _call_sizes(c=d) == 0
+
+
+SCRATCH_BYTES = 256 << 20   # INPC_NOALLOC_SCRATCH_BYTES
+
+
+def _noalloc(n, F=16, fdt=0, mode=1, camera=None):
+    c = pr.c_camera(camera or cam())
+    st = pr.c_settings(1e-4, mode, -1)
+    return pr.lib().inpc_rasterize_fwd_noalloc(FAKE, FAKE, fdt, FAKE, n, F, ctypes.byref(c), ctypes.byref(st),
+                                               FAKE, FAKE, None, None)
+
+
+def _noalloc_fits(n, camera, F, fdt):
+    fws, sv, _ = pr.plain_sizes(n, camera, F, fdt, 1)
+    return ((sv + 255) // 256) * 256 + fws <= SCRATCH_BYTES
+
+
+def test_noalloc_forward_rejects_on_the_host():
+    """The no-allocation forward refuses, before touching the device, a
+    problem whose recompute-mode state and workspace exceed the fixed
+    scratch (INPC_ESCRATCH) and a SAVE-mode request (no state is kept)."""
+    hd = workloads.canonical_camera(1920, 1080)
+    assert not _noalloc_fits(2_000_000, hd, 16, 0)
+    assert _noalloc(2_000_000, camera=hd) == -6
+    assert _noalloc(100, mode=0) == -1
+    assert _noalloc(100, F=0) == -3
+    # the sizes the header quotes as fitting
+    assert _noalloc_fits(1_370_000, workloads.canonical_camera(1280, 720), 8, 0)
+    assert _noalloc_fits(870_000, hd, 16, 0) and not _noalloc_fits(880_000, hd, 16, 0)
+    assert _noalloc_fits(1_190_000, hd, 16, 1) and not _noalloc_fits(1_200_000, hd, 16, 1)
