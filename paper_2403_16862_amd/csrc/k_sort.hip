@@ -285,23 +285,50 @@ void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, cons
 bool sort_valid(int digit, int items) { return pass_fn(digit, items) != nullptr; }
 
 // ------------------------------------------------------------ pixel ranges
+// One thread per group of kRangeGroup consecutive sorted keys (read with
+// 16-byte loads) and the key in front of the group: every position i whose
+// key differs from the one before starts the range of key[i] and ends the
+// range of key[i-1].  Bins without keys keep the [0, 0) the fill gave them.
+constexpr int kRangeGroup = 8;
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ m_dev,
                                                 uint32_t m_bound, uint2* __restrict__ range) {
     const uint32_t m = live_count(m_dev, m_bound);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const uint32_t k = keys[i];
-    if (i == 0 || keys[i - 1] != k) range[k].x = i;
-    if (i + 1 == m || keys[i + 1] != k) range[k].y = i + 1;
+    const uint32_t i0 = (blockIdx.x * blockDim.x + threadIdx.x) * (uint32_t)kRangeGroup;
+    if (i0 >= m) return;
+    uint32_t k[kRangeGroup];
+    if (i0 + kRangeGroup <= m) {
+        const uint4 a = reinterpret_cast<const uint4*>(keys + i0)[0];
+        const uint4 b = reinterpret_cast<const uint4*>(keys + i0)[1];
+        k[0] = a.x; k[1] = a.y; k[2] = a.z; k[3] = a.w;
+        k[4] = b.x; k[5] = b.y; k[6] = b.z; k[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kRangeGroup; ++j) k[j] = i0 + j < m ? keys[i0 + j] : 0u;
+    }
+    uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRangeGroup; ++j) {
+        const uint32_t i = i0 + (uint32_t)j;
+        if (i < m) {
+            if (i == 0u || k[j] != prev) {
+                range[k[j]].x = i;
+                if (i > 0u) range[prev].y = i;
+            }
+            if (i + 1u == m) range[k[j]].y = m;
+            prev = k[j];
+        }
+    }
 }
 
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
                    int64_t n_pixels, uint2* range, hipStream_t s) {
     launch_fill_u32(reinterpret_cast<uint32_t*>(range), 0u, (size_t)n_pixels * 2, s);
     if (m_bound == 0) return;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((m_bound + 255) / 256)), dim3(256), 0, s,
-                       pkey_sorted, m_dev, (uint32_t)m_bound, range);
+    const int64_t groups = (m_bound + kRangeGroup - 1) / kRangeGroup;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, pkey_sorted, m_dev,
+                       (uint32_t)m_bound, range);
 }
 
 // ------------------------------------------------------------ tile order
@@ -359,8 +386,56 @@ __global__ __launch_bounds__(256) void k_order_place(const uint2* __restrict__ r
     if (t < n_tiles) perm[base[c] + local] = (uint32_t)t;
 }
 
+// Up to kOrderOneBlock tiles: the whole order in one block of 1024 threads.
+// The classes of all tiles are read once (8 loads in flight per thread) and
+// kept in LDS as bytes; a class histogram, its scan (largest class first)
+// and the placement follow in LDS.
+constexpr int kOrderOneBlock = 65536;
+constexpr int kOrderThreads = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_one_block(const uint2* __restrict__ range, int n_tiles,
+                                                                   uint32_t* __restrict__ perm) {
+    __shared__ unsigned char cls[kOrderOneBlock];
+    __shared__ uint32_t h[kOrderClasses];
+    for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) h[i] = 0u;
+    __syncthreads();
+    constexpr int U = 8;
+    for (int base = 0; base < n_tiles; base += U * kOrderThreads) {
+        uint2 rg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = base + u * kOrderThreads + (int)threadIdx.x;
+            rg[u] = t < n_tiles ? range[t] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = base + u * kOrderThreads + (int)threadIdx.x;
+            if (t < n_tiles) {
+                const int c = size_class(rg[u]);
+                cls[t] = (unsigned char)c;
+                atomicAdd(&h[c], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = kOrderClasses - 1; c >= 0; --c) {
+            const uint32_t n = h[c];
+            h[c] = run;
+            run += n;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_tiles; t += kOrderThreads) perm[atomicAdd(&h[cls[t]], 1u)] = (uint32_t)t;
+}
+
 void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* cls_tmp, uint32_t* perm, hipStream_t s) {
     if (n_tiles == 0) return;
+    if (n_tiles <= kOrderOneBlock) {
+        hipLaunchKernelGGL(k_order_one_block, dim3(1), dim3(kOrderThreads), 0, s, range, (int)n_tiles, perm);
+        return;
+    }
     const unsigned blocks = (unsigned)((n_tiles + 255) / 256);
     launch_fill_u32(cls_tmp, 0u, kOrderClasses, s);
     hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, s, range, n_tiles, cls_tmp);
