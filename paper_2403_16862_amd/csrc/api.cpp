@@ -21,22 +21,22 @@ namespace inpc {
 // zdigit / pdigit = 0: choose the digit width from the key width (fewest
 // passes of at most 9 bits, then the narrowest digit for that many passes).
 static const Tuning kTunings[] = {
-    {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
-    {0, 0, 16, kTileShape8, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 1 lane/pixel, bwd 2"},
-    {0, 0, 16, kTileShape8x2, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, 2 lanes/pixel"},
-    {0, 0, 32, kTileShape8, kTileShape8, "auto digits, 8192-key tiles, tile-list blend 8x8 (entries per tile)"},
-    {0, 0, 16, kTileShape16, kTileShape16, "auto digits, 4096-key tiles, tile-list blend 16x16 (entries per tile)"},
-    {0, 0, 16, kTileShape8x4, kTileShape8x4, "auto digits, 4096-key tiles, tile-list blend 8x8, 4 lanes/pixel"},
-    {0, 0, 16, kTileShape8x4, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 4 lanes/pixel, bwd 1"},
-    {0, 0, 16, 3, 4, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
-    {0, 0, 16, 3, 3, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 8 lanes/pixel 4x2"},
-    {0, 0, 16, 4, 4, "auto digits, 4096-key tiles, blend fwd 16 lanes/pixel 2x2, bwd 16 lanes/pixel 2x2"},
-    {0, 0, 32, 3, 4, "auto digits, 8192-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
-    {8, 8, 16, 3, 4, "depth sort 8-bit, pixel sort 8-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
-    {9, 11, 16, 3, 4, "depth sort 9-bit, pixel sort 11-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
-    {0, 0, 16, 2, 2, "auto digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
-    {0, 0, 16, 1, 1, "auto digits, 4096-key tiles, blend 2 lanes/pixel 8x4"},
-    {0, 0, 16, 0, 0, "auto digits, 4096-key tiles, blend 1 lane/pixel 8x8"},
+    {0, 0, 8, kTileShape8, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8 (entries per tile)"},
+    {0, 0, 8, kTileShape8, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 1 lane/pixel, bwd 2"},
+    {0, 0, 8, kTileShape8x2, kTileShape8x2, "auto digits, 4096-key tiles, tile-list blend 8x8, 2 lanes/pixel"},
+    {0, 0, 16, kTileShape8, kTileShape8, "auto digits, 8192-key tiles, tile-list blend 8x8 (entries per tile)"},
+    {0, 0, 8, kTileShape16, kTileShape16, "auto digits, 4096-key tiles, tile-list blend 16x16 (entries per tile)"},
+    {0, 0, 8, kTileShape8x4, kTileShape8x4, "auto digits, 4096-key tiles, tile-list blend 8x8, 4 lanes/pixel"},
+    {0, 0, 8, kTileShape8x4, kTileShape8, "auto digits, 4096-key tiles, tile-list blend 8x8, fwd 4 lanes/pixel, bwd 1"},
+    {0, 0, 8, 3, 4, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
+    {0, 0, 8, 3, 3, "auto digits, 4096-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 8 lanes/pixel 4x2"},
+    {0, 0, 8, 4, 4, "auto digits, 4096-key tiles, blend fwd 16 lanes/pixel 2x2, bwd 16 lanes/pixel 2x2"},
+    {0, 0, 16, 3, 4, "auto digits, 8192-key tiles, blend fwd 8 lanes/pixel 4x2, bwd 16 lanes/pixel 2x2"},
+    {8, 8, 8, 3, 4, "depth sort 8-bit, pixel sort 8-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
+    {9, 11, 8, 3, 4, "depth sort 9-bit, pixel sort 11-bit, 4096-key tiles, blend fwd 8, bwd 16 lanes/pixel"},
+    {0, 0, 8, 2, 2, "auto digits, 4096-key tiles, blend 4 lanes/pixel 4x4"},
+    {0, 0, 8, 1, 1, "auto digits, 4096-key tiles, blend 2 lanes/pixel 8x4"},
+    {0, 0, 8, 0, 0, "auto digits, 4096-key tiles, blend 1 lane/pixel 8x8"},
 };
 
 int auto_digit(int bits) {
@@ -213,6 +213,7 @@ struct BuildOffsets {  // transient buffers of the fragment build
 struct Layout {
     size_t saved_bytes, fwd_bytes, bwd_bytes;
     size_t s_state, s_scalars;
+    size_t s_views;             // SAVE mode: the device view table the backward reuses
     FragOffsets saved_frag;     // valid in SAVE mode (offsets into saved)
     FragOffsets fwd_frag;       // RECOMPUTE: offsets into fwd ws
     FragOffsets bwd_frag;       // RECOMPUTE: offsets into bwd ws
@@ -266,7 +267,10 @@ static Layout make_layout(const Problem& pb) {
     Carver s, f, b;
     L.s_state = s.take((size_t)pb.n_pixels * sizeof(PixelState));
     L.s_scalars = s.take(256);
-    if (pb.mode == INPC_SAVE) carve_frag(s, pb, L.saved_frag);
+    if (pb.mode == INPC_SAVE) {
+        L.s_views = s.take(pb.views.size() * sizeof(GpuView));
+        carve_frag(s, pb, L.saved_frag);
+    }
     carve_build(f, pb, L.fwd_build);
     if (pb.mode == INPC_RECOMPUTE) carve_frag(f, pb, L.fwd_frag, false);
     L.b_views = b.take(pb.views.size() * sizeof(GpuView));
@@ -401,11 +405,13 @@ static int saved_tuning(const void* saved) {
 // are sorted on the points (all splats of a point share its depth), so the
 // splat-level sort only runs the pixel digits; together the passes form one
 // stable LSD radix sort of the 64-bit (pixel << 32 | depth) keys.
+// views: where the device view table goes (the saved state in SAVE mode, so
+// that the backward reuses it).  m_dev[0] receives M, m_dev[1] the layout
+// code of the lists (0: per-pixel lists, else the tile blend shape).
 static void build_fragments(const Problem& pb, const Tuning& tn, const float* xyz,
                             const float* opacity, const void* feat, void* frag_base, const FragOffsets& fo,
-                            void* build_base, const BuildOffsets& bo, uint32_t* m_dev,
+                            void* build_base, const BuildOffsets& bo, GpuView* views, uint32_t* m_dev,
                             hipStream_t s) {
-    GpuView* views = at<GpuView>(build_base, bo.views);
     const int nv = (int)pb.views.size();
     launch_upload_views(pb.views.data(), nv, views, s);
     PointRec* rec = at<PointRec>(frag_base, fo.rec);
@@ -445,12 +451,15 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* pv_b = (pp & 1) ? pv_other : ids_final;
     {
         ProfScope p(kStEmit, s);
+        uint32_t* range_words = reinterpret_cast<uint32_t*>(at<uint2>(frag_base, fo.range));
+        const size_t n_range_words = (size_t)(tile ? pb.n_tiles : pb.n_pixels) * 2;
         if (tile)
             launch_tile_emit(zv_sorted, rec, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
-                             at<uint32_t>(build_base, bo.chunks), m_dev, pk_b, pv_b, s);
+                             at<uint32_t>(build_base, bo.chunks), m_dev, pk_b, pv_b, (uint32_t)tn.blend_shape,
+                             range_words, n_range_words, s);
         else
             launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
-                        pv_b, s);
+                        pv_b, range_words, n_range_words, s);
     }
     {
         ProfScope p(kStPixelSort, s);
@@ -461,7 +470,7 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     {
         ProfScope p(kStRanges, s);
         launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, tile ? pb.n_tiles : pb.n_pixels,
-                      at<uint2>(frag_base, fo.range), s);
+                      at<uint2>(frag_base, fo.range), true, s);
         if (tile)
             launch_tile_order(at<uint2>(frag_base, fo.range), pb.n_tiles, at<uint32_t>(build_base, bo.order),
                               at<uint32_t>(frag_base, fo.perm), s);
@@ -479,25 +488,24 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     uint32_t* m_dev = at<uint32_t>(saved, L.s_scalars);
     void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
-    build_fragments(pb, tn, xyz, opacity, feat, frag_base, fo, ws, L.fwd_build, m_dev, s);
+    GpuView* views = pb.mode == INPC_SAVE ? at<GpuView>(saved, L.s_views) : at<GpuView>(ws, L.fwd_build.views);
+    build_fragments(pb, tn, xyz, opacity, feat, frag_base, fo, ws, L.fwd_build, views, m_dev, s);
     // Per-splat blend weights (indexed by splat id) reuse the pixel sort's
     // spare value buffer, which is dead once the sort has finished.
     float* splat_weight = blend_weight ? at<float>(ws, L.fwd_build.pv_other) : nullptr;
     if (splat_weight)
         launch_fill_u32(reinterpret_cast<uint32_t*>(splat_weight), 0u, (size_t)4 * pb.n_vp, s);
-    // word 1 of the scalars records which fragment layout the state holds
-    launch_fill_u32(m_dev + 1, is_tile_shape(tn.blend_shape) ? (uint32_t)tn.blend_shape : 0u, 1, s);
     {
         ProfScope p(kStBlendFwd, s);
         float* tk = pb.mode == INPC_SAVE ? at<float>(frag_base, fo.tk) : nullptr;
         if (is_tile_shape(tn.blend_shape))
-            launch_tile_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
+            launch_tile_fwd(pb.F, pb.fdt, tn.blend_shape, views,
                             (int)pb.views.size(), pb.n_tiles, at<uint32_t>(frag_base, fo.perm),
                             at<uint2>(frag_base, fo.range), at<uint32_t>(frag_base, fo.ids),
                             at<unsigned char>(frag_base, fo.payload), payload_stride(pb.F, pb.fdt), tau, image, t_final,
                             at<PixelState>(saved, L.s_state), reinterpret_cast<float4*>(tk), splat_weight, s);
         else
-            launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, at<GpuView>(ws, L.fwd_build.views),
+            launch_blend_fwd(pb.F, pb.fdt, tn.blend_shape, views,
                              (int)pb.views.size(), pb.n_tiles, at<uint2>(frag_base, fo.range),
                              at<uint32_t>(frag_base, fo.ids), at<PointRec>(frag_base, fo.rec), feat, tau,
                              image, t_final, at<PixelState>(saved, L.s_state), tk, splat_weight, s);
@@ -522,15 +530,24 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     const void* frag_base;
     const FragOffsets* fo;
     const GpuView* views;
+    const int bshape = bwd_shape_of(tid, pb.mode);
     if (pb.mode == INPC_SAVE) {
-        launch_upload_views(pb.views.data(), (int)pb.views.size(), at<GpuView>(ws, L.b_views), s);
-        views = at<GpuView>(ws, L.b_views);
+        // The forward left its device view table in the saved state; its tile
+        // grid is the forward blend's, so a backward blend with other block
+        // dimensions uploads its own table.
+        if (blend_block_w(bshape) == blend_block_w(tn.blend_shape) &&
+            blend_block_h(bshape) == blend_block_h(tn.blend_shape)) {
+            views = at<GpuView>(sv, L.s_views);
+        } else {
+            launch_upload_views(pb.views.data(), (int)pb.views.size(), at<GpuView>(ws, L.b_views), s);
+            views = at<GpuView>(ws, L.b_views);
+        }
         frag_base = saved;
         fo = &L.saved_frag;
     } else {
         // Rebuild the fragment state exactly as the forward did.
         build_fragments(pb, tn, xyz, opacity, feat, ws, L.bwd_frag, ws, L.bwd_build,
-                        at<uint32_t>(ws, L.bwd_build.scalars), s);
+                        at<GpuView>(ws, L.bwd_build.views), at<uint32_t>(ws, L.bwd_build.scalars), s);
         views = at<GpuView>(ws, L.bwd_build.views);
         frag_base = ws;
         fo = &L.bwd_frag;
@@ -540,7 +557,6 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
         ProfScope p(kStClearRecords, s);
         launch_fill_u32(reinterpret_cast<uint32_t*>(frec), 0u, (size_t)8 * pb.n_vp, s);
     }
-    const int bshape = bwd_shape_of(tid, pb.mode);
     {
     ProfScope p(kStBlendBwd, s);
     if (is_tile_shape(bshape))

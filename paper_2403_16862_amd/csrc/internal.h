@@ -14,7 +14,7 @@ namespace inpc {
 struct Tuning {
     int zdigit;       // digit bits of the per-point depth sort (0: from the key width)
     int pdigit;       // digit bits of the per-fragment pixel sort (0: from the key width)
-    int sort_items;   // keys per thread in a sort tile (tile = 256 * items)
+    int sort_items;   // keys per thread in a sort tile (tile = 512 * items)
     int blend_shape;  // forward blend: lanes per pixel and wave tile, see blend_shape_dims()
     int bwd_shape;    // backward blend shape
     const char* name;
@@ -69,13 +69,17 @@ inline int payload_stride(int F, int feat_dtype) {
 constexpr int kEmitBlock = 256;
 constexpr int kEmitItems = 4;
 size_t emit_chunks(int64_t n_vp);
+// m_dev[0] receives the fragment count M, m_dev[1] the layout code (0 here,
+// the tile shape for tile entries); the count kernel also clears
+// clear_words words at clear (the range array of the later ranges kernel).
 void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev,
-                 uint32_t* pkey, uint32_t* pid, hipStream_t s);
+                 uint32_t* pkey, uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s);
 // Tile entries of depth-sorted view points: (global tile id, view point).
 void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
-                      uint32_t* tkey, uint32_t* tval, hipStream_t s);
+                      uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
+                      hipStream_t s);
 
 // Stable LSD radix sort of (u32 key, u32 value) pairs over key bits
 // [0, bits).  n_dev (may be null) holds the live element count on the
@@ -92,8 +96,9 @@ int radix_passes(int digit, int bits);
 bool sort_valid(int digit, int items);
 
 // Per-pixel [start, end) ranges of the pixel-sorted fragment keys.
+// ``cleared``: the range array already holds zeros (cleared by the emission).
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
-                   int64_t n_pixels, uint2* range, hipStream_t s);
+                   int64_t n_pixels, uint2* range, bool cleared, hipStream_t s);
 
 // Tile dispatch order: perm[0, n_tiles) lists the tiles by descending entry
 // count class (bit length of the count), so the blends start the heaviest

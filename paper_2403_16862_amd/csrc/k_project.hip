@@ -210,11 +210,25 @@ __device__ __forceinline__ uint32_t items_of(uint32_t zval) {
     return TILE ? (zval >> 28) : (uint32_t)__popc(zval >> 28);
 }
 
+// Besides counting, the blocks clear ``clear_words`` words at ``clear`` (the
+// range array the ranges kernel fills after the sort), so no separate fill
+// launch is needed.
 template <bool TILE>
 __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __restrict__ zval,
                                                            int64_t n_vp,
-                                                           uint32_t* __restrict__ chunk_cnt) {
+                                                           uint32_t* __restrict__ chunk_cnt,
+                                                           uint32_t* __restrict__ clear, size_t clear_words) {
     __shared__ uint32_t s_tmp[kEmitBlock / kWave];
+    {
+        const size_t stride = (size_t)gridDim.x * kEmitBlock * 4;
+        for (size_t i = ((size_t)blockIdx.x * kEmitBlock + threadIdx.x) * 4; i < clear_words; i += stride) {
+            if (i + 4 <= clear_words) {
+                reinterpret_cast<uint4*>(clear + i)[0] = make_uint4(0u, 0u, 0u, 0u);
+            } else {
+                for (size_t j = i; j < clear_words; ++j) clear[j] = 0u;
+            }
+        }
+    }
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
     uint32_t cnt = 0;
 #pragma unroll
@@ -226,9 +240,9 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __res
 }
 
 // Exclusive scan of the chunk counts in one block; writes the total (the
-// fragment count M) to m_dev.
+// fragment count M) to m_dev[0] and the layout code of the lists to m_dev[1].
 __global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt, size_t n,
-                                                      uint32_t* __restrict__ m_dev) {
+                                                      uint32_t* __restrict__ m_dev, uint32_t layout) {
     __shared__ uint32_t s_tmp[1024 / kWave];
     uint32_t running = 0;
     for (size_t base = 0; base < n; base += 1024) {
@@ -239,7 +253,10 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt
         if (i < n) cnt[i] = running + ex;
         running += total;
     }
-    if (threadIdx.x == 0) *m_dev = running;
+    if (threadIdx.x == 0) {
+        m_dev[0] = running;
+        m_dev[1] = layout;
+    }
 }
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
@@ -290,15 +307,16 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
 
 void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev, uint32_t* pkey,
-                 uint32_t* pid, hipStream_t s) {
+                 uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s) {
     const size_t chunks = emit_chunks(n_vp);
     if (chunks == 0) {
-        launch_fill_u32(m_dev, 0u, 1, s);
+        launch_fill_u32(m_dev, 0u, 2, s);
+        launch_fill_u32(clear, 0u, clear_words, s);
         return;
     }
     hipLaunchKernelGGL(k_emit_count<false>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       n_vp, chunk_cnt);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev);
+                       n_vp, chunk_cnt, clear, clear_words);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, 0u);
     hipLaunchKernelGGL(k_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
                        rec, views, n_views, n_vp, chunk_cnt, pkey, pid);
 }
@@ -363,15 +381,18 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
 
 void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
-                      uint32_t* tkey, uint32_t* tval, hipStream_t s) {
+                      uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
+                      hipStream_t s) {
     const size_t chunks = emit_chunks(n_vp);
     if (chunks == 0) {
         launch_fill_u32(m_dev, 0u, 1, s);
+        launch_fill_u32(m_dev + 1, layout, 1, s);
+        launch_fill_u32(clear, 0u, clear_words, s);
         return;
     }
     hipLaunchKernelGGL(k_emit_count<true>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       n_vp, chunk_cnt);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev);
+                       n_vp, chunk_cnt, clear, clear_words);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, layout);
     hipLaunchKernelGGL(k_tile_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
                        rec, views, n_views, n_vp, tile_log2, chunk_cnt, tkey, tval);
 }

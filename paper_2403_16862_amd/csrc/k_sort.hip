@@ -16,7 +16,7 @@
 
 namespace inpc {
 
-constexpr int kSortBlock = 256;
+constexpr int kSortBlock = 512;   // 8 waves per sort tile
 constexpr uint32_t kXcdGroup = 8;   // consecutive downsweep tiles per XCD
 
 static inline size_t tiles_for(int items, int64_t n) {
@@ -57,11 +57,17 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __
     const int w = threadIdx.x / kWave, lane = __lane_id();
     const uint32_t base = tile * TILE + w * (ITEMS * kWave);
     uint32_t* h = s_hist[w];
-#pragma unroll 4
+    uint32_t kk[ITEMS];   // every key of the thread in flight before the first is counted
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = base + it * kWave + lane;
+        kk[it] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
         const bool valid = idx < n;
-        const uint32_t d = valid ? (keys[idx] >> shift) & (BINS - 1) : 0u;
+        const uint32_t d = valid ? (kk[it] >> shift) & (BINS - 1) : 0u;
         const uint64_t act = __ballot(valid);
         const uint32_t d0 = __shfl(d, 0);
         const uint64_t same = __ballot(valid && d == d0);
@@ -253,10 +259,10 @@ using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, 
 static PassFn pass_fn(int digit, int items) {
 #define INPC_CASE(D, I) \
     if (digit == D && items == I) return &sort_pass<D, I>;
-    INPC_CASE(7, 16) INPC_CASE(7, 32)
-    INPC_CASE(8, 8) INPC_CASE(8, 16) INPC_CASE(8, 32)
-    INPC_CASE(9, 16) INPC_CASE(9, 32)
-    INPC_CASE(10, 16)
+    INPC_CASE(7, 8) INPC_CASE(7, 16)
+    INPC_CASE(8, 8) INPC_CASE(8, 16)
+    INPC_CASE(9, 8) INPC_CASE(9, 16)
+    INPC_CASE(10, 8)
     INPC_CASE(11, 8) INPC_CASE(11, 16)
 #undef INPC_CASE
     return nullptr;
@@ -323,8 +329,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 }
 
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
-                   int64_t n_pixels, uint2* range, hipStream_t s) {
-    launch_fill_u32(reinterpret_cast<uint32_t*>(range), 0u, (size_t)n_pixels * 2, s);
+                   int64_t n_pixels, uint2* range, bool cleared, hipStream_t s) {
+    if (!cleared) launch_fill_u32(reinterpret_cast<uint32_t*>(range), 0u, (size_t)n_pixels * 2, s);
     if (m_bound == 0) return;
     const int64_t groups = (m_bound + kRangeGroup - 1) / kRangeGroup;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, pkey_sorted, m_dev,
