@@ -430,10 +430,12 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     uint32_t* zk_b = at<uint32_t>(build_base, bo.zk_b);
     uint32_t* zv_b = at<uint32_t>(build_base, bo.zv_b);
     uint32_t* counts = at<uint32_t>(build_base, bo.counts);
+    uint32_t* n_live = at<uint32_t>(build_base, bo.scalars) + 4;   // view points with splats, after the depth sort
     {
         ProfScope p(kStDepthSort, s);
+        // points without splats (key zkey_none) leave the sort in its first pass
         launch_radix_sort(zdigit_of(tn, pb.zbits), tn.sort_items, pb.zbits, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b,
-                          nullptr, pb.n_vp, counts, s);
+                          nullptr, pb.n_vp, counts, s, pb.zkey_none, n_live);
     }
     const int zp = radix_passes(zdigit_of(tn, pb.zbits), pb.zbits);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
@@ -454,11 +456,11 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
         uint32_t* range_words = reinterpret_cast<uint32_t*>(at<uint2>(frag_base, fo.range));
         const size_t n_range_words = (size_t)(tile ? pb.n_tiles : pb.n_pixels) * 2;
         if (tile)
-            launch_tile_emit(zv_sorted, rec, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
+            launch_tile_emit(zv_sorted, n_live, rec, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
                              at<uint32_t>(build_base, bo.chunks), m_dev, pk_b, pv_b, (uint32_t)tn.blend_shape,
                              range_words, n_range_words, s);
         else
-            launch_emit(zv_sorted, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
+            launch_emit(zv_sorted, n_live, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
                         pv_b, range_words, n_range_words, s);
     }
     {

@@ -72,11 +72,12 @@ size_t emit_chunks(int64_t n_vp);
 // m_dev[0] receives the fragment count M, m_dev[1] the layout code (0 here,
 // the tile shape for tile entries); the count kernel also clears
 // clear_words words at clear (the range array of the later ranges kernel).
-void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+// n_live: device count of the sorted view points to read (nullptr: n_vp).
+void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev,
                  uint32_t* pkey, uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s);
 // Tile entries of depth-sorted view points: (global tile id, view point).
-void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
                       uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
                       hipStream_t s);
@@ -89,9 +90,13 @@ void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const Gp
 // and in (kb, vb) after an even number (in (kin, vin) after none).
 // (kin, vin) may alias (kb, vb).  counts holds sort_counts_words() words.
 size_t sort_counts_words(int digit, int items, int64_t n_bound);
+// live_out != nullptr: the first pass leaves out the keys equal to drop_key
+// and writes how many it kept to *live_out; the later passes and the result
+// hold only those (the result is *live_out keys long).
 void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
                        uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
-                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s);
+                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s,
+                       uint32_t drop_key = 0u, uint32_t* live_out = nullptr);
 int radix_passes(int digit, int bits);
 bool sort_valid(int digit, int items);
 

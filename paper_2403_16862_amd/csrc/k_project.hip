@@ -203,6 +203,14 @@ constexpr int kChunk = kEmitBlock * kEmitItems;
 
 size_t emit_chunks(int64_t n_vp) { return (size_t)((n_vp + kChunk - 1) / kChunk); }
 
+// Sorted view points that take part: the depth sort leaves out the points
+// without splats and writes how many it kept to *n_live (at most n_vp).
+__device__ __forceinline__ int64_t live_points(const uint32_t* n_live, int64_t n_vp) {
+    if (!n_live) return n_vp;
+    const int64_t n = (int64_t)*n_live;
+    return n < n_vp ? n : n_vp;
+}
+
 // Items per view point: the corner count (popcount of the mask) or, for tile
 // entries, the count itself.
 template <bool TILE>
@@ -216,6 +224,7 @@ __device__ __forceinline__ uint32_t items_of(uint32_t zval) {
 template <bool TILE>
 __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __restrict__ zval,
                                                            int64_t n_vp,
+                                                           const uint32_t* __restrict__ n_live,
                                                            uint32_t* __restrict__ chunk_cnt,
                                                            uint32_t* __restrict__ clear, size_t clear_words) {
     __shared__ uint32_t s_tmp[kEmitBlock / kWave];
@@ -229,11 +238,12 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __res
             }
         }
     }
+    const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i)
-        if (base + i < n_vp) cnt += items_of<TILE>(zval[base + i]);
+        if (base + i < live) cnt += items_of<TILE>(zval[base + i]);
     uint32_t total;
     block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
     if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = total;
@@ -261,18 +271,19 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
     const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
-    const GpuView* __restrict__ views, int n_views, int64_t n_vp,
+    const GpuView* __restrict__ views, int n_views, int64_t n_vp, const uint32_t* __restrict__ n_live,
     const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ pkey,
     uint32_t* __restrict__ pid) {
     __shared__ uint32_t s_tmp[kEmitBlock / kWave];
     __shared__ uint32_t s_key[4 * kChunk];
     __shared__ uint32_t s_id[4 * kChunk];
+    const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
     uint32_t vals[kEmitItems];
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
-        vals[i] = (base + i < n_vp) ? zval[base + i] : 0u;
+        vals[i] = (base + i < live) ? zval[base + i] : 0u;
         cnt += __popc(vals[i] >> 28);
     }
     uint32_t total;
@@ -305,7 +316,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
     }
 }
 
-void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev, uint32_t* pkey,
                  uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s) {
     const size_t chunks = emit_chunks(n_vp);
@@ -315,10 +326,10 @@ void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView
         return;
     }
     hipLaunchKernelGGL(k_emit_count<false>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       n_vp, chunk_cnt, clear, clear_words);
+                       n_vp, n_live, chunk_cnt, clear, clear_words);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, 0u);
     hipLaunchKernelGGL(k_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       rec, views, n_views, n_vp, chunk_cnt, pkey, pid);
+                       rec, views, n_views, n_vp, n_live, chunk_cnt, pkey, pid);
 }
 
 // Tile entries: one (tile, view point) pair per distinct square tile of
@@ -327,18 +338,19 @@ void launch_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView
 // (tiles of one point in ascending corner order of first appearance).
 __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
-    const GpuView* __restrict__ views, int n_views, int64_t n_vp, int lg,
+    const GpuView* __restrict__ views, int n_views, int64_t n_vp, const uint32_t* __restrict__ n_live, int lg,
     const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ tkey,
     uint32_t* __restrict__ tval) {
     __shared__ uint32_t s_tmp[kEmitBlock / kWave];
     __shared__ uint32_t s_key[4 * kChunk];
     __shared__ uint32_t s_id[4 * kChunk];
+    const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
     uint32_t vals[kEmitItems];
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
-        vals[i] = (base + i < n_vp) ? zval[base + i] : 0u;
+        vals[i] = (base + i < live) ? zval[base + i] : 0u;
         cnt += vals[i] >> 28;
     }
     uint32_t total;
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     }
 }
 
-void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const GpuView* views,
+void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
                       uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
                       hipStream_t s) {
@@ -391,10 +403,10 @@ void launch_tile_emit(const uint32_t* zval_sorted, const PointRec* rec, const Gp
         return;
     }
     hipLaunchKernelGGL(k_emit_count<true>, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       n_vp, chunk_cnt, clear, clear_words);
+                       n_vp, n_live, chunk_cnt, clear, clear_words);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, layout);
     hipLaunchKernelGGL(k_tile_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       rec, views, n_views, n_vp, tile_log2, chunk_cnt, tkey, tval);
+                       rec, views, n_views, n_vp, n_live, tile_log2, chunk_cnt, tkey, tval);
 }
 
 }  // namespace inpc

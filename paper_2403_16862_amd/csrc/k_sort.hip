@@ -36,12 +36,13 @@ __device__ __forceinline__ uint32_t live_count(const uint32_t* n_dev, uint32_t n
     return n < n_bound ? n : n_bound;
 }
 
+// drop: keys equal to drop_key are left out (counted nowhere, written nowhere).
 template <int D, int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               uint32_t n_bound, int shift,
                                                               uint32_t* __restrict__ counts,
-                                                              uint32_t stride) {
+                                                              uint32_t stride, bool drop, uint32_t drop_key) {
     // One LDS histogram per wave.  A row whose lanes all carry the same digit
     // (common once the lower digits are sorted) costs a single update; other
     // rows use per-lane LDS atomics.
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
-        const bool valid = idx < n;
+        const bool valid = idx < n && !(drop && kk[it] == drop_key);
         const uint32_t d = valid ? (kk[it] >> shift) & (BINS - 1) : 0u;
         const uint64_t act = __ballot(valid);
         const uint32_t d0 = __shfl(d, 0);
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev,
     uint32_t n_bound, int shift, const uint32_t* __restrict__ row_prefix, uint32_t stride,
-    const uint32_t* __restrict__ bin_total) {
+    const uint32_t* __restrict__ bin_total, bool drop, uint32_t drop_key, uint32_t* __restrict__ live_out) {
     constexpr int BINS = 1 << D;
     constexpr int WAVES = kSortBlock / kWave;
     constexpr int TILE = kSortBlock * ITEMS;
@@ -153,10 +154,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         val[it] = valid ? vin[idx] : 0u;
     }
     // Rows are processed in input order, so ranks within a wave are stable.
+    uint32_t keep = 0u;   // bit it: item it takes part in this pass
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
-        const bool valid = idx < n;
+        const bool valid = idx < n && !(drop && key[it] == drop_key);
+        keep |= valid ? (1u << it) : 0u;
         const uint32_t d = (key[it] >> shift) & (BINS - 1);
         const uint64_t peers = match_digit<D>(d, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
@@ -189,8 +192,8 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     // Exclusive scans over digits (digits are owned thread-major: thread t
     // owns digits t, t+256, ...): of this tile's digit totals (LDS slots) and
     // of the global digit totals of the pass (where each digit starts).
+    uint32_t running = 0, running_g = 0;   // end: kept items of the tile, of the pass
     {
-        uint32_t running = 0, running_g = 0;
 #pragma unroll
         for (int j = 0; j < (BINS + kSortBlock - 1) / kSortBlock; ++j) {
             const int d = threadIdx.x + j * kSortBlock;
@@ -206,11 +209,12 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
             running_g += total_g;
         }
     }
+    // the live count of the following passes: every block knows it, tile 0 writes it
+    if (live_out && tile == 0u && threadIdx.x == 0) *live_out = running_g;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-        const uint32_t idx = base + it * kWave + lane;
-        if (idx < n) {
+        if ((keep >> it) & 1u) {
             const uint32_t d = (key[it] >> shift) & (BINS - 1);
             const uint32_t slot = s_start[d] + s_cnt[w][d] + rank[it];
             s_key[slot] = key[it];
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         }
     }
     __syncthreads();
-    const uint32_t tile_n = (n - tile * TILE) < (uint32_t)TILE ? (n - tile * TILE) : (uint32_t)TILE;
+    const uint32_t tile_n = running;
     for (uint32_t j = threadIdx.x; j < tile_n; j += kSortBlock) {
         const uint32_t k = s_key[j];
         const uint32_t d = (k >> shift) & (BINS - 1);
@@ -231,14 +235,14 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
 template <int D, int ITEMS>
 static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
                       const uint32_t* n_dev, int64_t n_bound, int shift, uint32_t* counts,
-                      hipStream_t s) {
+                      bool drop, uint32_t drop_key, uint32_t* live_out, hipStream_t s) {
     const size_t tiles = tiles_for(ITEMS, n_bound);
     const uint32_t stride = (uint32_t)tiles + 1;
     uint32_t* totals = counts + ((size_t)1 << D) * stride;
     {
         ProfScope p(kStSortUpsweep, s);
         hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
-                           kin, n_dev, (uint32_t)n_bound, shift, counts, stride);
+                           kin, n_dev, (uint32_t)n_bound, shift, counts, stride, drop, drop_key);
     }
     {
         ProfScope p(kStSortScan, s);
@@ -249,12 +253,13 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
         ProfScope p(kStSortDownsweep, s);
         const size_t grid = (tiles + 8 * kXcdGroup - 1) / (8 * kXcdGroup) * (8 * kXcdGroup);
         hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
-                           kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals);
+                           kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
+                           drop, drop_key, live_out);
     }
 }
 
 using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const uint32_t*,
-                        int64_t, int, uint32_t*, hipStream_t);
+                        int64_t, int, uint32_t*, bool, uint32_t, uint32_t*, hipStream_t);
 
 static PassFn pass_fn(int digit, int items) {
 #define INPC_CASE(D, I) \
@@ -270,17 +275,27 @@ static PassFn pass_fn(int digit, int items) {
 
 // Pass 0 reads (kin, vin) and writes (ka, va); later passes alternate
 // (ka, va) -> (kb, vb) -> (ka, va) ...  (kin, vin) may alias (kb, vb).
+// live_out != nullptr: pass 0 leaves out every key equal to drop_key and
+// writes the number of kept keys to *live_out, which bounds the later passes
+// (the sorted result is that many keys long).
 void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
                        uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
-                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s) {
+                       const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s,
+                       uint32_t drop_key, uint32_t* live_out) {
     const int passes = radix_passes(digit, bits);
-    if (n_bound == 0 || passes == 0) return;
+    if (n_bound == 0 || passes == 0) {
+        // nothing sorted: every key stays where it is (keys to drop included)
+        if (live_out) launch_fill_u32(live_out, (uint32_t)n_bound, 1, s);
+        return;
+    }
     PassFn fn = pass_fn(digit, items);
     const uint32_t* ki = kin;
     const uint32_t* vi = vin;
     uint32_t *ko = ka, *vo = va;
     for (int p = 0; p < passes; ++p) {
-        fn(ki, vi, ko, vo, n_dev, n_bound, p * digit, counts, s);
+        const bool drop = p == 0 && live_out != nullptr;
+        fn(ki, vi, ko, vo, p > 0 && live_out ? live_out : n_dev, n_bound, p * digit, counts, drop, drop_key,
+           drop ? live_out : nullptr, s);
         ki = ko;
         vi = vo;
         ko = (ko == ka) ? kb : ka;
