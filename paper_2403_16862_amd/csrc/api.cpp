@@ -259,7 +259,7 @@ static void carve_build(Carver& c, const Problem& pb, BuildOffsets& b) {
     b.pk_b = c.take(mb * 4);
     b.pv_other = c.take(mb * 4);
     b.counts = c.take(max_counts_words(pb) * 4);
-    b.order = c.take(256);
+    b.order = c.take(512);   // tile-order counters (66 words)
 }
 
 static Layout make_layout(const Problem& pb) {
@@ -472,7 +472,7 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     {
         ProfScope p(kStRanges, s);
         launch_ranges(pk_sorted, m_dev, 4 * pb.n_vp, tile ? pb.n_tiles : pb.n_pixels,
-                      at<uint2>(frag_base, fo.range), true, s);
+                      at<uint2>(frag_base, fo.range), true, tile ? at<uint32_t>(build_base, bo.order) : nullptr, s);
         if (tile)
             launch_tile_order(at<uint2>(frag_base, fo.range), pb.n_tiles, at<uint32_t>(build_base, bo.order),
                               at<uint32_t>(frag_base, fo.perm), s);

@@ -102,13 +102,14 @@ bool sort_valid(int digit, int items);
 
 // Per-pixel [start, end) ranges of the pixel-sorted fragment keys.
 // ``cleared``: the range array already holds zeros (cleared by the emission).
+// order_tmp (may be null): the tile order's 66 counter words, cleared here.
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
-                   int64_t n_pixels, uint2* range, bool cleared, hipStream_t s);
+                   int64_t n_pixels, uint2* range, bool cleared, uint32_t* order_tmp, hipStream_t s);
 
 // Tile dispatch order: perm[0, n_tiles) lists the tiles by descending entry
 // count class (bit length of the count), so the blends start the heaviest
-// tiles first.  cls_tmp: 33 words of scratch.
-void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* cls_tmp, uint32_t* perm, hipStream_t s);
+// tiles first.  order_tmp: the 66 counter words launch_ranges cleared.
+void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* order_tmp, uint32_t* perm, hipStream_t s);
 
 // Per-pixel state kept from the forward blend for the backward.
 struct alignas(16) PixelState {

@@ -36,13 +36,13 @@ __device__ __forceinline__ uint32_t live_count(const uint32_t* n_dev, uint32_t n
     return n < n_bound ? n : n_bound;
 }
 
-// drop: keys equal to drop_key are left out (counted nowhere, written nowhere).
-template <int D, int ITEMS>
+// DROP: keys equal to drop_key are left out (counted nowhere, written nowhere).
+template <int D, int ITEMS, bool DROP>
 __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                               const uint32_t* __restrict__ n_dev,
                                                               uint32_t n_bound, int shift,
                                                               uint32_t* __restrict__ counts,
-                                                              uint32_t stride, bool drop, uint32_t drop_key) {
+                                                              uint32_t stride, uint32_t drop_key) {
     // One LDS histogram per wave.  A row whose lanes all carry the same digit
     // (common once the lower digits are sorted) costs a single update; other
     // rows use per-lane LDS atomics.
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_upsweep(const uint32_t* __
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
-        const bool valid = idx < n && !(drop && kk[it] == drop_key);
+        const bool valid = idx < n && !(DROP && kk[it] == drop_key);
         const uint32_t d = valid ? (kk[it] >> shift) & (BINS - 1) : 0u;
         const uint64_t act = __ballot(valid);
         const uint32_t d0 = __shfl(d, 0);
@@ -116,12 +116,12 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_rows(uint32_t* __restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = running;
 }
 
-template <int D, int ITEMS>
+template <int D, int ITEMS, bool DROP>
 __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev,
     uint32_t n_bound, int shift, const uint32_t* __restrict__ row_prefix, uint32_t stride,
-    const uint32_t* __restrict__ bin_total, bool drop, uint32_t drop_key, uint32_t* __restrict__ live_out) {
+    const uint32_t* __restrict__ bin_total, uint32_t drop_key, uint32_t* __restrict__ live_out) {
     constexpr int BINS = 1 << D;
     constexpr int WAVES = kSortBlock / kWave;
     constexpr int TILE = kSortBlock * ITEMS;
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     __shared__ uint32_t s_key[TILE];
     __shared__ uint32_t s_val[TILE];
     __shared__ uint32_t s_tmp[WAVES];
+    __shared__ uint32_t s_tile_n;             // DROP: items of the tile that take part in the pass
 
     const uint32_t n = live_count(n_dev, n_bound);
     // Runs of consecutive groups of kXcdGroup tiles go to one XCD (blocks are
@@ -154,12 +155,10 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         val[it] = valid ? vin[idx] : 0u;
     }
     // Rows are processed in input order, so ranks within a wave are stable.
-    uint32_t keep = 0u;   // bit it: item it takes part in this pass
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
-        const bool valid = idx < n && !(drop && key[it] == drop_key);
-        keep |= valid ? (1u << it) : 0u;
+        const bool valid = idx < n && !(DROP && key[it] == drop_key);
         const uint32_t d = (key[it] >> shift) & (BINS - 1);
         const uint64_t peers = match_digit<D>(d, valid);
         const uint32_t below = (uint32_t)__popcll(peers & lanemask_lt());
@@ -192,8 +191,8 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     // Exclusive scans over digits (digits are owned thread-major: thread t
     // owns digits t, t+256, ...): of this tile's digit totals (LDS slots) and
     // of the global digit totals of the pass (where each digit starts).
-    uint32_t running = 0, running_g = 0;   // end: kept items of the tile, of the pass
     {
+        uint32_t running = 0, running_g = 0;   // end: kept items of the tile, of the pass
 #pragma unroll
         for (int j = 0; j < (BINS + kSortBlock - 1) / kSortBlock; ++j) {
             const int d = threadIdx.x + j * kSortBlock;
@@ -208,13 +207,17 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
             running += total;
             running_g += total_g;
         }
+        if (DROP && threadIdx.x == 0) {
+            s_tile_n = running;
+            // the live count of the following passes: every block knows it, tile 0 writes it
+            if (tile == 0u) *live_out = running_g;
+        }
     }
-    // the live count of the following passes: every block knows it, tile 0 writes it
-    if (live_out && tile == 0u && threadIdx.x == 0) *live_out = running_g;
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
-        if ((keep >> it) & 1u) {
+        const uint32_t idx = base + it * kWave + lane;
+        if (idx < n && !(DROP && key[it] == drop_key)) {
             const uint32_t d = (key[it] >> shift) & (BINS - 1);
             const uint32_t slot = s_start[d] + s_cnt[w][d] + rank[it];
             s_key[slot] = key[it];
@@ -222,7 +225,9 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         }
     }
     __syncthreads();
-    const uint32_t tile_n = running;
+    uint32_t tile_n;
+    if constexpr (DROP) tile_n = s_tile_n;
+    else tile_n = (n - tile * TILE) < (uint32_t)TILE ? (n - tile * TILE) : (uint32_t)TILE;
     for (uint32_t j = threadIdx.x; j < tile_n; j += kSortBlock) {
         const uint32_t k = s_key[j];
         const uint32_t d = (k >> shift) & (BINS - 1);
@@ -241,8 +246,12 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     uint32_t* totals = counts + ((size_t)1 << D) * stride;
     {
         ProfScope p(kStSortUpsweep, s);
-        hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
-                           kin, n_dev, (uint32_t)n_bound, shift, counts, stride, drop, drop_key);
+        if (drop)
+            hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS, true>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                               kin, n_dev, (uint32_t)n_bound, shift, counts, stride, drop_key);
+        else
+            hipLaunchKernelGGL((k_radix_upsweep<D, ITEMS, false>), dim3((unsigned)tiles), dim3(kSortBlock), 0, s,
+                               kin, n_dev, (uint32_t)n_bound, shift, counts, stride, drop_key);
     }
     {
         ProfScope p(kStSortScan, s);
@@ -252,9 +261,14 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     {
         ProfScope p(kStSortDownsweep, s);
         const size_t grid = (tiles + 8 * kXcdGroup - 1) / (8 * kXcdGroup) * (8 * kXcdGroup);
-        hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
-                           kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
-                           drop, drop_key, live_out);
+        if (drop)
+            hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS, true>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
+                               kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
+                               drop_key, live_out);
+        else
+            hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS, false>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
+                               kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
+                               drop_key, nullptr);
     }
 }
 
@@ -314,7 +328,9 @@ constexpr int kRangeGroup = 8;
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ m_dev,
-                                                uint32_t m_bound, uint2* __restrict__ range) {
+                                                uint32_t m_bound, uint2* __restrict__ range,
+                                                uint32_t* __restrict__ clear, int clear_words) {
+    if (clear && blockIdx.x == 0 && (int)threadIdx.x < clear_words) clear[threadIdx.x] = 0u;
     const uint32_t m = live_count(m_dev, m_bound);
     const uint32_t i0 = (blockIdx.x * blockDim.x + threadIdx.x) * (uint32_t)kRangeGroup;
     if (i0 >= m) return;
@@ -343,13 +359,18 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
     }
 }
 
+constexpr int kOrderWords = 66;   // class counts, class cursors (tile order)
+
 void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m_bound,
-                   int64_t n_pixels, uint2* range, bool cleared, hipStream_t s) {
+                   int64_t n_pixels, uint2* range, bool cleared, uint32_t* order_tmp, hipStream_t s) {
     if (!cleared) launch_fill_u32(reinterpret_cast<uint32_t*>(range), 0u, (size_t)n_pixels * 2, s);
-    if (m_bound == 0) return;
+    if (m_bound == 0) {
+        if (order_tmp) launch_fill_u32(order_tmp, 0u, kOrderWords, s);
+        return;
+    }
     const int64_t groups = (m_bound + kRangeGroup - 1) / kRangeGroup;
     hipLaunchKernelGGL(k_ranges, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, pkey_sorted, m_dev,
-                       (uint32_t)m_bound, range);
+                       (uint32_t)m_bound, range, order_tmp, order_tmp ? kOrderWords : 0);
 }
 
 // ------------------------------------------------------------ tile order
@@ -357,8 +378,13 @@ void launch_ranges(const uint32_t* pkey_sorted, const uint32_t* m_dev, int64_t m
 // becomes the tail of a blend launch.  perm lists the tiles by descending
 // size class (class = bit length of the entry count), so the heaviest tiles
 // start first.  The order inside a class is arbitrary (atomics): every tile
-// is blended on its own, so results do not depend on it.
+// is blended on its own, so results do not depend on it.  Two kernels: a
+// class histogram (one global atomic per block and class), and the
+// placement, where every block derives the class starts from the histogram
+// and reserves its slots with one atomic per class.  The counters are
+// cleared by the ranges kernel.
 constexpr int kOrderClasses = 33;
+static_assert(2 * kOrderClasses <= kOrderWords, "order counters");
 
 __device__ __forceinline__ int size_class(const uint2 rg) {
     const uint32_t n = rg.y - rg.x;
@@ -377,18 +403,9 @@ __global__ __launch_bounds__(256) void k_order_hist(const uint2* __restrict__ ra
         if (h[i]) atomicAdd(&cls_cnt[i], h[i]);
 }
 
-// cls_cnt -> start of each class in perm, largest class first.
-__global__ void k_order_scan(uint32_t* __restrict__ cls_cnt) {
-    if (threadIdx.x != 0) return;
-    uint32_t run = 0;
-    for (int c = kOrderClasses - 1; c >= 0; --c) {
-        const uint32_t n = cls_cnt[c];
-        cls_cnt[c] = run;
-        run += n;
-    }
-}
-
+// cls_cnt: class counts (read); cls_next: per-class cursors from 0 (advanced).
 __global__ __launch_bounds__(256) void k_order_place(const uint2* __restrict__ range, int64_t n_tiles,
+                                                     const uint32_t* __restrict__ cls_cnt,
                                                      uint32_t* __restrict__ cls_next, uint32_t* __restrict__ perm) {
     __shared__ uint32_t h[kOrderClasses];
     __shared__ uint32_t base[kOrderClasses];
@@ -402,66 +419,23 @@ __global__ __launch_bounds__(256) void k_order_place(const uint2* __restrict__ r
         local = atomicAdd(&h[c], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kOrderClasses; i += 256) base[i] = h[i] ? atomicAdd(&cls_next[i], h[i]) : 0u;
+    if (threadIdx.x == 0) {
+        uint32_t start = 0;   // classes from the largest down
+        for (int k = kOrderClasses - 1; k >= 0; --k) {
+            base[k] = h[k] ? start + atomicAdd(&cls_next[k], h[k]) : 0u;
+            start += cls_cnt[k];
+        }
+    }
     __syncthreads();
     if (t < n_tiles) perm[base[c] + local] = (uint32_t)t;
 }
 
-// Up to kOrderOneBlock tiles: the whole order in one block of 1024 threads.
-// The classes of all tiles are read once (8 loads in flight per thread) and
-// kept in LDS as bytes; a class histogram, its scan (largest class first)
-// and the placement follow in LDS.
-constexpr int kOrderOneBlock = 65536;
-constexpr int kOrderThreads = 1024;
-
-__global__ __launch_bounds__(kOrderThreads) void k_order_one_block(const uint2* __restrict__ range, int n_tiles,
-                                                                   uint32_t* __restrict__ perm) {
-    __shared__ unsigned char cls[kOrderOneBlock];
-    __shared__ uint32_t h[kOrderClasses];
-    for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) h[i] = 0u;
-    __syncthreads();
-    constexpr int U = 8;
-    for (int base = 0; base < n_tiles; base += U * kOrderThreads) {
-        uint2 rg[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = base + u * kOrderThreads + (int)threadIdx.x;
-            rg[u] = t < n_tiles ? range[t] : make_uint2(0u, 0u);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = base + u * kOrderThreads + (int)threadIdx.x;
-            if (t < n_tiles) {
-                const int c = size_class(rg[u]);
-                cls[t] = (unsigned char)c;
-                atomicAdd(&h[c], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int c = kOrderClasses - 1; c >= 0; --c) {
-            const uint32_t n = h[c];
-            h[c] = run;
-            run += n;
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < n_tiles; t += kOrderThreads) perm[atomicAdd(&h[cls[t]], 1u)] = (uint32_t)t;
-}
-
-void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* cls_tmp, uint32_t* perm, hipStream_t s) {
+void launch_tile_order(const uint2* range, int64_t n_tiles, uint32_t* order_tmp, uint32_t* perm, hipStream_t s) {
     if (n_tiles == 0) return;
-    if (n_tiles <= kOrderOneBlock) {
-        hipLaunchKernelGGL(k_order_one_block, dim3(1), dim3(kOrderThreads), 0, s, range, (int)n_tiles, perm);
-        return;
-    }
     const unsigned blocks = (unsigned)((n_tiles + 255) / 256);
-    launch_fill_u32(cls_tmp, 0u, kOrderClasses, s);
-    hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, s, range, n_tiles, cls_tmp);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, cls_tmp);
-    hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, s, range, n_tiles, cls_tmp, perm);
+    hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, s, range, n_tiles, order_tmp);
+    hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, s, range, n_tiles, order_tmp,
+                       order_tmp + kOrderClasses, perm);
 }
 
 }  // namespace inpc

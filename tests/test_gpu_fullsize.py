@@ -55,11 +55,10 @@ def test_config3_full_autograd_with_fd():
     H.check_blend_weight(bw.cpu().numpy(), L, s.opa, n_gpu)
 
 
-def test_config4_batched_graph_all_views():
-    """All 16 views of the timed graph replay: splat lists bit-exact, image and
-    transmittance within 1e-5 of the oracle on the bfloat16-rounded features,
-    within 1e-2 of the oracle on the unrounded float32 features, gradients
-    against the oracle's adjoint."""
+@pytest.fixture(scope="module")
+def config4_replay():
+    """The 16-view batched bfloat16 workload as one graph replay (the timed
+    form): sorted lists, blend counts, images, transmittances and gradients."""
     b = workloads.config4()
     views = pr.make_views(b.cams, b.point_offset, b.point_count)
     g = np.concatenate([gi.reshape(-1, b.F) for gi in b.g_imgs])
@@ -70,41 +69,49 @@ def test_config4_batched_graph_all_views():
     step.replay()
     torch.cuda.synchronize()
     keys, ids, nb = pr.debug_fragments(step.state())
-    img = step.image.cpu().numpy()
-    tf = step.t_final.cpu().numpy()
-    gf, go = step.grad_feat.cpu().numpy(), step.grad_opa.cpu().numpy()
+    out = dict(b=b, g=g, keys=keys, ids=ids, nb=nb, img=step.image.cpu().numpy(), tf=step.t_final.cpu().numpy(),
+               gf=step.grad_feat.cpu().numpy(), go=step.grad_opa.cpu().numpy(), fbits=H.bf16_bits(b.feat))
+    del step, x, o, f
+    torch.cuda.empty_cache()
+    return out
+
+
+@pytest.mark.parametrize("view", range(16))
+def test_config4_batched_graph_view(config4_replay, view):
+    """One of the 16 views of the timed graph replay: splat list bit-exact,
+    image and transmittance within 1e-5 of the oracle on the bfloat16-rounded
+    features, within 1e-2 of the oracle on the unrounded float32 features,
+    gradients against the oracle's adjoint."""
+    r = config4_replay
+    b, v = r["b"], view
     P_v = [c.width * c.height for c in b.cams]
     pix_off = np.concatenate([[0], np.cumsum(P_v)]).astype(np.int64)
     vp_off = np.concatenate([[0], np.cumsum(b.point_count)]).astype(np.int64)
-    pix = keys >> np.uint64(32)
-    vbound = np.searchsorted(pix, pix_off.astype(np.uint64))     # keys are sorted by pixel
-    fbits = H.bf16_bits(b.feat)
-    worst = dict(img_rounded=0.0, img_unrounded=0.0, t_final=0.0)
-    for v in range(len(b.cams)):
-        sl = slice(b.point_offset[v], b.point_offset[v] + b.point_count[v])
-        L = oracle.fragments(b.xyz[sl], b.cams[v])
-        lo, hi = int(pix_off[v]), int(pix_off[v + 1])
-        a, e = int(vbound[v]), int(vbound[v + 1])
-        assert np.array_equal(keys[a:e], L.keys(lo))
-        assert np.array_equal(ids[a:e].astype(np.int64) - 4 * int(vp_off[v]), L.ids.astype(np.int64))
-        n_gpu = nb[lo:hi].astype(np.int32)
-        ref_t = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, want_t_after=True)
-        amb = H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
-        ref = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, n_override=n_gpu)
-        e_img = H.rel_err(img[lo:hi], ref["image"]).max()
-        e_t = H.rel_err(tf[lo:hi], ref["t_final"]).max()
-        assert e_img <= H.REL_TOL and e_t <= H.REL_TOL, (v, e_img, e_t)
-        unr = oracle.blend_forward(L, b.opa[sl], b.feat[sl], 1e-4, n_override=n_gpu)
-        e_unr = float(np.abs(img[lo:hi] - unr["image"]).max())
-        assert e_unr <= H.BF16_ABS_TOL, (v, e_unr)
-        rb = oracle.blend_backward(L, b.opa[sl], fbits[sl], n_gpu, g[lo:hi])
-        H.check_grads(gf[vp_off[v]:vp_off[v + 1]], go[vp_off[v]:vp_off[v + 1]], rb)
-        worst = dict(img_rounded=max(worst["img_rounded"], e_img), img_unrounded=max(worst["img_unrounded"], e_unr),
-                     t_final=max(worst["t_final"], e_t))
-        H.say(f"    view {v}: {b.cams[v].width}x{b.cams[v].height} N={b.point_count[v]} M={L.m} "
-              f"ambiguous={amb} ok")
-        del L, ref_t, ref, unr, rb
-    H.say(f"    worst over 16 views: {worst}")
+    vbound = np.searchsorted(r["keys"] >> np.uint64(32), pix_off.astype(np.uint64))   # keys are sorted by pixel
+    sl = slice(b.point_offset[v], b.point_offset[v] + b.point_count[v])
+    L = oracle.fragments(b.xyz[sl], b.cams[v])
+    lo, hi = int(pix_off[v]), int(pix_off[v + 1])
+    a, e = int(vbound[v]), int(vbound[v + 1])
+    assert np.array_equal(r["keys"][a:e], L.keys(lo))
+    assert np.array_equal(r["ids"][a:e].astype(np.int64) - 4 * int(vp_off[v]), L.ids.astype(np.int64))
+    n_gpu = r["nb"][lo:hi].astype(np.int32)
+    fbits = r["fbits"]
+    ref_t = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, want_t_after=True)
+    amb = H.termination_ok(L, ref_t["t_after"], n_gpu, ref_t["n_blended"], 1e-4)
+    del ref_t
+    ref = oracle.blend_forward(L, b.opa[sl], fbits[sl], 1e-4, n_override=n_gpu)
+    e_img = H.rel_err(r["img"][lo:hi], ref["image"]).max()
+    e_t = H.rel_err(r["tf"][lo:hi], ref["t_final"]).max()
+    assert e_img <= H.REL_TOL and e_t <= H.REL_TOL, (v, e_img, e_t)
+    del ref
+    unr = oracle.blend_forward(L, b.opa[sl], b.feat[sl], 1e-4, n_override=n_gpu)
+    e_unr = float(np.abs(r["img"][lo:hi] - unr["image"]).max())
+    assert e_unr <= H.BF16_ABS_TOL, (v, e_unr)
+    del unr
+    rb = oracle.blend_backward(L, b.opa[sl], fbits[sl], n_gpu, r["g"][lo:hi])
+    H.check_grads(r["gf"][vp_off[v]:vp_off[v + 1]], r["go"][vp_off[v]:vp_off[v + 1]], rb)
+    H.say(f"    view {v}: {b.cams[v].width}x{b.cams[v].height} N={b.point_count[v]} M={L.m} ambiguous={amb} "
+          f"image err {e_img:.2e} t_final err {e_t:.2e} unrounded-feature err {e_unr:.2e}")
 
 
 @pytest.fixture(scope="module")
@@ -128,41 +135,52 @@ def _check_pose(L, opa, feat, fbits, img, tf, n_gpu, label):
           f"t_final err {et:.2e} unrounded-feature err {eu:.2e}")
 
 
-def test_config5_all_poses_plain_and_aliased_batched(config5_scene):
-    """32M points (clusters plus a background shell), 8 poses on a circle,
-    bfloat16 features, forward only: every pose as a plain call, and the 8
-    poses as one batched call whose views all alias the same points."""
+@pytest.fixture(scope="module")
+def config5_batched(config5_scene):
+    """The 8 poses as one batched call whose views all alias the same points:
+    sorted lists, blend counts, images and transmittances on the host."""
     b = config5_scene
-    n = b.xyz.shape[0]
     x, o = H.to_dev(b.xyz), H.to_dev(b.opa)
     f = H.to_dev(b.feat).to(torch.bfloat16)
-    fbits = H.bf16_bits(b.feat)
     views = pr.make_views(b.cams, b.point_offset, b.point_count)
     img_b, tf_b, st_b = pr.rasterize_forward_batched(x, f, o, views, 1e-4, "save", keep_workspace=True)
     keys_b, ids_b, nb_b = pr.debug_fragments(st_b)
-    img_b, tf_b = img_b.cpu().numpy(), tf_b.cpu().numpy()
-    del st_b
+    out = dict(keys=keys_b, ids=ids_b, nb=nb_b, img=img_b.cpu().numpy(), tf=tf_b.cpu().numpy())
+    del st_b, img_b, tf_b, x, o, f
     torch.cuda.empty_cache()
-    P = b.cams[0].width * b.cams[0].height
-    vbound = np.searchsorted(keys_b >> np.uint64(32), (np.arange(len(b.cams) + 1) * P).astype(np.uint64))
-    H.say(f"  config 5: N={n}, 8 aliased views, {keys_b.shape[0]} splats in the batched call")
-    for v, cam in enumerate(b.cams):
-        img, tf, st = pr.rasterize_forward(x, f, o, cam, 1e-4, keep_workspace=True)
-        keys, ids, nb = pr.debug_fragments(st)
-        img, tf = img.reshape(-1, 16).cpu().numpy(), tf.reshape(-1).cpu().numpy()
-        del st
-        L = oracle.fragments(b.xyz, cam)
-        assert np.array_equal(keys, L.keys()) and np.array_equal(ids, L.ids), v
-        a, e = int(vbound[v]), int(vbound[v + 1])
-        assert np.array_equal(keys_b[a:e], L.keys(v * P)), v
-        assert np.array_equal(ids_b[a:e].astype(np.int64) - 4 * v * n, L.ids.astype(np.int64)), v
-        n_gpu = nb.astype(np.int32)
-        assert np.array_equal(nb_b[v * P:(v + 1) * P], nb), v
-        _check_pose(L, b.opa, b.feat, fbits, img, tf, n_gpu, f"pose {v} plain")
-        # the batched call blends the same lists with the same arithmetic
-        assert np.array_equal(img_b[v * P:(v + 1) * P], img) and np.array_equal(tf_b[v * P:(v + 1) * P], tf), v
-        H.say(f"    pose {v} batched: lists and blend counts equal the oracle's, image equal to the plain call")
-        del keys, ids, nb, L
+    H.say(f"  config 5: N={b.xyz.shape[0]}, 8 aliased views, {keys_b.shape[0]} splats in the batched call")
+    return out
+
+
+@pytest.mark.parametrize("pose", range(8))
+def test_config5_pose_plain_and_aliased_batched(config5_scene, config5_batched, pose):
+    """32M points (clusters plus a background shell), 8 poses on a circle,
+    bfloat16 features, forward only: this pose as a plain call against the
+    oracle, and its view of the batched call over 8 aliased views."""
+    b = config5_scene
+    v, cam = pose, b.cams[pose]
+    n = b.xyz.shape[0]
+    x, o = H.to_dev(b.xyz), H.to_dev(b.opa)
+    f = H.to_dev(b.feat).to(torch.bfloat16)
+    img, tf, st = pr.rasterize_forward(x, f, o, cam, 1e-4, keep_workspace=True)
+    keys, ids, nb = pr.debug_fragments(st)
+    img, tf = img.reshape(-1, 16).cpu().numpy(), tf.reshape(-1).cpu().numpy()
+    del st, x, o, f
+    torch.cuda.empty_cache()
+    L = oracle.fragments(b.xyz, cam)
+    assert np.array_equal(keys, L.keys()) and np.array_equal(ids, L.ids), v
+    P = cam.width * cam.height
+    bt = config5_batched
+    vbound = np.searchsorted(bt["keys"] >> np.uint64(32), np.array([v * P, (v + 1) * P], dtype=np.uint64))
+    a, e = int(vbound[0]), int(vbound[1])
+    assert np.array_equal(bt["keys"][a:e], L.keys(v * P)), v
+    assert np.array_equal(bt["ids"][a:e].astype(np.int64) - 4 * v * n, L.ids.astype(np.int64)), v
+    n_gpu = nb.astype(np.int32)
+    assert np.array_equal(bt["nb"][v * P:(v + 1) * P], nb), v
+    _check_pose(L, b.opa, b.feat, H.bf16_bits(b.feat), img, tf, n_gpu, f"pose {v} plain")
+    # the batched call blends the same lists with the same arithmetic
+    assert np.array_equal(bt["img"][v * P:(v + 1) * P], img) and np.array_equal(bt["tf"][v * P:(v + 1) * P], tf), v
+    H.say(f"    pose {v} batched: lists and blend counts equal the oracle's, image equal to the plain call")
 
 
 def test_config5_far_plane_1000(config5_scene):
