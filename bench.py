@@ -5,7 +5,8 @@ synthetic points at 1920x1080 with 16 float32 features, in fragments per
 second (fragments = splats the forward emits), with the HBM traffic of the
 step from rocprofv3 counters.  Also reported on the same JSON line:
 
-* per-stage timings measured with HIP events inside the timed steps;
+* per-stage timings measured with HIP events in a second set of steps
+  (the markers cost time, so they stay out of the timed steps);
 * the roofline figure of the dominant kernel under two byte models (the
   per-splat model, and the compulsory bytes of this design) and its counter
   traffic;
