@@ -595,7 +595,8 @@ def bench_config5(pr, torch, np, workloads, log, reps=5):
     """32M points (clusters + far shell), 1920x1080, F=16 bfloat16, forward
     only (no backward state: RECOMPUTE mode keeps none): 8 poses one after
     another, and the 8 poses as one batched call whose views alias the same
-    points; median of 5 event-timed runs each."""
+    points, each with the autotuner's choice; median of 5 event-timed runs
+    each."""
     t0 = time.time()
     b = workloads.config5()
     n = b.xyz.shape[0]
@@ -605,17 +606,22 @@ def bench_config5(pr, torch, np, workloads, log, reps=5):
     fb = torch.from_numpy(b.feat).to(dev).to(torch.bfloat16)
     o = torch.from_numpy(b.opa).to(dev)
     views = pr.make_views(b.cams, b.point_offset, b.point_count)
+    # the autotuner's choice for each form (forward only)
+    t_seq, _ = pr.autotune(x, fb, o, pr.make_views([b.cams[0]], [0], [n]), repeats=1)
+    torch.cuda.empty_cache()
+    t_bat, _ = pr.autotune(x, fb, o, views, repeats=1)
+    torch.cuda.empty_cache()
 
     def seq():
         for cam in b.cams:
-            pr.rasterize_forward(x, fb, o, cam, 1e-4, "recompute")
+            pr.rasterize_forward(x, fb, o, cam, 1e-4, "recompute", t_seq)
 
     def batched():
-        pr.rasterize_forward_batched(x, fb, o, views, 1e-4, "recompute")
+        pr.rasterize_forward_batched(x, fb, o, views, 1e-4, "recompute", t_bat)
 
     ms_seq = event_ms(torch, seq, reps=reps, warm=1)
     ms_bat = event_ms(torch, batched, reps=reps, warm=1)
-    _, _, st = pr.rasterize_forward_batched(x, fb, o, views, 1e-4, "save", keep_workspace=True)
+    _, _, st = pr.rasterize_forward_batched(x, fb, o, views, 1e-4, "save", t_bat, keep_workspace=True)
     M = pr.fragment_count(st)
     del st
     torch.cuda.empty_cache()
@@ -625,7 +631,8 @@ def bench_config5(pr, torch, np, workloads, log, reps=5):
            "ms_8_poses_sequential": round(ms_seq, 4), "ms_8_poses_batched": round(ms_bat, 4),
            "ms_per_pose_sequential": round(ms_seq / len(b.cams), 4),
            "fragments_per_s_sequential": round(M / (ms_seq * 1e-3), 1),
-           "fragments_per_s_batched": round(M / (ms_bat * 1e-3), 1)}
+           "fragments_per_s_batched": round(M / (ms_bat * 1e-3), 1),
+           "tuning_sequential": t_seq, "tuning_batched": t_bat}
     log(f"config 5: {json.dumps(out)}")
     return out
 

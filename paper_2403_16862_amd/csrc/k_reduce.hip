@@ -91,6 +91,67 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     if (blend_weight) blend_weight[vp] = (float)bw;
 }
 
+// The same reduction with S = FM / 4 lanes per point, lane s owning
+// features 4s .. 4s+3: one wave load then covers the 64-byte gradient rows of
+// 16 points (whole rows, 16 lines) instead of one 16-byte piece of each of 64
+// rows, and the gradient rows are stored as one contiguous run per wave.
+// Every lane forms the point's terms in the same order as above, so the
+// results are bit-identical; lane 0 of the point writes the scalars.
+template <int FM>
+__global__ __launch_bounds__(256) void k_point_reduce_q(
+    const GpuView* __restrict__ views, int n_views, int64_t n_vp, const PointRec* __restrict__ rec,
+    const float2* __restrict__ frec, const float* __restrict__ g_img, float* __restrict__ grad_feat,
+    float* __restrict__ grad_opa, float* __restrict__ blend_weight) {
+    constexpr int S = FM / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t vp = t / S;
+    const int sub = (int)(t % S);
+    if (vp >= n_vp) return;
+    const int v = n_views == 1 ? 0
+                               : find_view(views, n_views, vp, [](const GpuView& g) { return g.vpoint_offset; });
+    const int64_t pix0 = views[v].pixel_offset;
+    const int64_t W = views[v].W;
+    const PointRec pr = rec[vp];
+    const float4 r01 = reinterpret_cast<const float4*>(frec)[2 * vp];
+    const float4 r23 = reinterpret_cast<const float4*>(frec)[2 * vp + 1];
+    const uint32_t mask = anc_mask(pr.anc);
+    const float da[4] = {r01.x, r01.z, r23.x, r23.z};
+    const float ta[4] = {r01.y, r01.w, r23.y, r23.w};
+    const int x0 = anc_x0(pr.anc), y0 = anc_y0(pr.anc);
+    const int cf = mask != 0u ? __builtin_ctz(mask) : 0;
+    float4 g[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int cc = ((mask >> c) & 1u) ? c : cf;
+        const int64_t q = mask != 0u ? pix0 + (int64_t)(y0 + (cc >> 1)) * W + (x0 + (cc & 1)) : pix0;
+        g[c] = reinterpret_cast<const float4*>(g_img + q * FM)[sub];
+    }
+    double gf[4] = {0.0, 0.0, 0.0, 0.0};
+    double go = 0.0, bw = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const bool on = (mask >> c) & 1u;
+        float wx, wy;
+        corner_factors(pr.ax, pr.ay, c, wx, wy);
+        const double go2 = __builtin_fma((double)wx * (double)wy, (double)da[c], go);
+        const double bw2 = __builtin_fma((double)wx * (double)wy, (double)ta[c], bw);
+        go = on ? go2 : go;
+        bw = on ? bw2 : bw;
+        const float gc[4] = {g[c].x, g[c].y, g[c].z, g[c].w};
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double x = __builtin_fma((double)ta[c], (double)gc[f], gf[f]);
+            gf[f] = on ? x : gf[f];
+        }
+    }
+    reinterpret_cast<float4*>(grad_feat + vp * FM)[sub] =
+        make_float4((float)gf[0], (float)gf[1], (float)gf[2], (float)gf[3]);
+    if (sub == 0) {
+        grad_opa[vp] = (float)go;
+        if (blend_weight) blend_weight[vp] = (float)bw;
+    }
+}
+
 // ------------------------------------------------ per-point blend weight
 // b[vp] = sum over the existing corners c (ascending) of w_c * T_c alpha_c:
 // the splat blend weights of Eq. 1 combined with the bilinear weights as
@@ -202,6 +263,20 @@ void launch_point_reduce(int F, const GpuView* views, int n_views, int64_t n_vp,
                          const PointRec* rec, const float2* frec, const float* g_img,
                          float* grad_feat, float* grad_opa, float* blend_weight, hipStream_t s) {
     if (n_vp == 0) return;
+    // rows of 8, 16 or 32 float32 (16-byte aligned): F / 4 lanes per point,
+    // while the grid stays below 2^31 work items
+    if ((F == 8 || F == 16 || F == 32) && n_vp <= ((int64_t)1 << 31) / (F / 4)) {
+        const int64_t threads = n_vp * (F / 4);
+        const unsigned qblocks = (unsigned)((threads + 255) / 256);
+        auto q = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(qblocks), dim3(256), 0, s, views, n_views, n_vp, rec, frec, g_img,
+                               grad_feat, grad_opa, blend_weight);
+        };
+        if (F == 8) q(k_point_reduce_q<8>);
+        else if (F == 16) q(k_point_reduce_q<16>);
+        else q(k_point_reduce_q<32>);
+        return;
+    }
     const unsigned blocks = (unsigned)((n_vp + 255) / 256);
     dispatch_f(F, [&]<int FM, bool DYN>() {
         hipLaunchKernelGGL((k_point_reduce<FM, DYN>), dim3(blocks), dim3(256), 0, s, views, n_views, n_vp,
