@@ -417,10 +417,16 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     PointRec* rec = at<PointRec>(frag_base, fo.rec);
     uint32_t* zk_in = at<uint32_t>(build_base, bo.zk_in);
     uint32_t* zv_in = at<uint32_t>(build_base, bo.zv_in);
+    // The anchor words (in, and the two sort buffers) sit in the pixel sort's
+    // first key buffer (4 n_vp words), which is unused until the emission
+    // has read them.
+    uint32_t* za_in = at<uint32_t>(build_base, bo.pk_a);
+    uint32_t* za_a = za_in + pb.n_vp;
+    uint32_t* za_b = za_a + pb.n_vp;
     const bool tile = is_tile_shape(tn.blend_shape);
     {
         ProfScope p(kStProject, s);
-        launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in,
+        launch_project(xyz, opacity, views, nv, pb.n_vp, pb.zbase, pb.zkey_none, rec, zk_in, zv_in, za_in,
                        tile ? tile_log2_of(tn.blend_shape) : 0, feat, pb.F * (pb.fdt == INPC_BF16 ? 2 : 4),
                        tile ? at<unsigned char>(frag_base, fo.payload) : nullptr, payload_stride(pb.F, pb.fdt),
                        s);
@@ -435,10 +441,11 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
         ProfScope p(kStDepthSort, s);
         // points without splats (key zkey_none) leave the sort in its first pass
         launch_radix_sort(zdigit_of(tn, pb.zbits), tn.sort_items, pb.zbits, zk_in, zv_in, zk_a, zv_a, zk_b, zv_b,
-                          nullptr, pb.n_vp, counts, s, pb.zkey_none, n_live);
+                          nullptr, pb.n_vp, counts, s, pb.zkey_none, n_live, za_in, za_a, za_b);
     }
     const int zp = radix_passes(zdigit_of(tn, pb.zbits), pb.zbits);
     const uint32_t* zv_sorted = zp == 0 ? zv_in : ((zp & 1) ? zv_a : zv_b);
+    const uint32_t* za_sorted = zp == 0 ? za_in : ((zp & 1) ? za_a : za_b);
 
     // Pixel sort (or tile sort of tile entries): emission writes (kb, vb);
     // the sorted values must end in the fragment-state id buffer.
@@ -456,11 +463,11 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
         uint32_t* range_words = reinterpret_cast<uint32_t*>(at<uint2>(frag_base, fo.range));
         const size_t n_range_words = (size_t)(tile ? pb.n_tiles : pb.n_pixels) * 2;
         if (tile)
-            launch_tile_emit(zv_sorted, n_live, rec, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
+            launch_tile_emit(zv_sorted, n_live, za_sorted, views, nv, pb.n_vp, tile_log2_of(tn.blend_shape),
                              at<uint32_t>(build_base, bo.chunks), m_dev, pk_b, pv_b, (uint32_t)tn.blend_shape,
                              range_words, n_range_words, s);
         else
-            launch_emit(zv_sorted, n_live, rec, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
+            launch_emit(zv_sorted, n_live, za_sorted, views, nv, pb.n_vp, at<uint32_t>(build_base, bo.chunks), m_dev, pk_b,
                         pv_b, range_words, n_range_words, s);
     }
     {

@@ -51,11 +51,13 @@ void launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 
 // zval = vp | hb << 28 with hb the corner mask, or (tile_log2 > 0) the
 // number of 2^tile_log2-pixel square tiles the point's splats touch.
-// payload (may be null): per view point, the record followed by the feature
-// row (stored type), ps bytes per point, written for points with splats.
+// zanc = the record's anchor word (its own array, so that the depth sort can
+// carry it to the emission).  payload (may be null): per view point, the
+// record followed by the feature row (stored type), ps bytes per point,
+// written for points with splats.
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, int tile_log2, const void* feat, int feat_row_bytes,
+                    uint32_t* zval, uint32_t* zanc, int tile_log2, const void* feat, int feat_row_bytes,
                     unsigned char* payload, int ps, hipStream_t s);
 
 // Bytes per view point of the record + feature payload (64-byte multiple, so
@@ -72,12 +74,13 @@ size_t emit_chunks(int64_t n_vp);
 // m_dev[0] receives the fragment count M, m_dev[1] the layout code (0 here,
 // the tile shape for tile entries); the count kernel also clears
 // clear_words words at clear (the range array of the later ranges kernel).
-// n_live: device count of the sorted view points to read (nullptr: n_vp).
-void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
+// n_live: device count of the sorted view points to read (nullptr: n_vp);
+// anc_sorted: their anchor words, in the same order.
+void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const uint32_t* anc_sorted, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev,
                  uint32_t* pkey, uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s);
 // Tile entries of depth-sorted view points: (global tile id, view point).
-void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
+void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const uint32_t* anc_sorted, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
                       uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
                       hipStream_t s);
@@ -92,11 +95,14 @@ void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const
 size_t sort_counts_words(int digit, int items, int64_t n_bound);
 // live_out != nullptr: the first pass leaves out the keys equal to drop_key
 // and writes how many it kept to *live_out; the later passes and the result
-// hold only those (the result is *live_out keys long).
+// hold only those (the result is *live_out keys long).  ain != nullptr: a
+// second value per key, permuted with the pairs through aa / ab the way the
+// values go through va / vb (three distinct arrays); required with live_out.
 void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
                        uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                        const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s,
-                       uint32_t drop_key = 0u, uint32_t* live_out = nullptr);
+                       uint32_t drop_key = 0u, uint32_t* live_out = nullptr, const uint32_t* ain = nullptr,
+                       uint32_t* aa = nullptr, uint32_t* ab = nullptr);
 int radix_passes(int digit, int bits);
 bool sort_valid(int digit, int items);
 

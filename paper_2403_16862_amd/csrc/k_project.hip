@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
                                                  int64_t n_vp, uint32_t zbase, uint32_t zkey_none,
                                                  PointRec* __restrict__ rec,
                                                  uint32_t* __restrict__ zkey,
-                                                 uint32_t* __restrict__ zval, int tile_log2,
+                                                 uint32_t* __restrict__ zval,
+                                                 uint32_t* __restrict__ zanc, int tile_log2,
                                                  const unsigned char* __restrict__ feat, int frow,
                                                  unsigned char* __restrict__ payload, int ps) {
     __shared__ PointRec s_rec[256];
@@ -138,6 +139,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
         const uint32_t m = anc_mask(r.anc);
         const uint32_t hb = tile_log2 ? (m ? tile_entries(anc_x0(r.anc), anc_y0(r.anc), m, tile_log2) : 0u) : m;
         zval[vp] = (uint32_t)vp | (hb << 28);
+        zanc[vp] = r.anc;
         if (!m) arow = -1;
     }
     if (!payload) return;
@@ -186,19 +188,22 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
 
 void launch_project(const float* xyz, const float* opa, const GpuView* views, int n_views,
                     int64_t n_vp, uint32_t zbase, uint32_t zkey_none, PointRec* rec, uint32_t* zkey,
-                    uint32_t* zval, int tile_log2, const void* feat, int feat_row_bytes,
+                    uint32_t* zval, uint32_t* zanc, int tile_log2, const void* feat, int feat_row_bytes,
                     unsigned char* payload, int ps, hipStream_t s) {
     if (n_vp == 0) return;
     const int64_t blocks = (n_vp + 255) / 256;
     hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, s, xyz, opa, views, n_views,
-                       n_vp, zbase, zkey_none, rec, zkey, zval, tile_log2,
+                       n_vp, zbase, zkey_none, rec, zkey, zval, zanc, tile_log2,
                        reinterpret_cast<const unsigned char*>(feat), feat_row_bytes, payload, ps);
 }
 
 // ----------------------------------------------------------------- emission
 // Fragments are emitted in the order of the depth-sorted points, corners in
 // ascending order, so the emitted sequence is ordered by (depth, splat id).
-// Count -> exclusive scan of chunk counts -> order-preserving write.
+// Count -> exclusive scan of chunk counts -> order-preserving write.  Each
+// point's anchor word travels with it through the depth sort, so the write
+// reads it in sorted order instead of gathering it by view point (one
+// 128-byte line per point).
 constexpr int kChunk = kEmitBlock * kEmitItems;
 
 size_t emit_chunks(int64_t n_vp) { return (size_t)((n_vp + kChunk - 1) / kChunk); }
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt
 }
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
-    const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
+    const uint32_t* __restrict__ zval, const uint32_t* __restrict__ zanc,
     const GpuView* __restrict__ views, int n_views, int64_t n_vp, const uint32_t* __restrict__ n_live,
     const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ pkey,
     uint32_t* __restrict__ pid) {
@@ -279,30 +284,39 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
     __shared__ uint32_t s_id[4 * kChunk];
     const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
-    uint32_t vals[kEmitItems];
+    uint32_t vals[kEmitItems], anc[kEmitItems];
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
-        vals[i] = (base + i < live) ? zval[base + i] : 0u;
+        const bool in = base + i < live;
+        vals[i] = in ? zval[base + i] : 0u;
+        anc[i] = in ? zanc[base + i] : 0u;
         cnt += __popc(vals[i] >> 28);
     }
     uint32_t total;
     uint32_t pos = block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
+    int64_t pix0 = 0, W0 = 0;
+    if (n_views == 1) {
+        pix0 = views[0].pixel_offset;
+        W0 = views[0].W;
+    }
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
         const uint32_t mask = vals[i] >> 28;
         if (mask == 0u) continue;
         const uint32_t vp = vals[i] & kVpMask;
-        const PointRec r = rec[vp];
-        const int v = n_views == 1 ? 0
-                                   : find_view(views, n_views, (int64_t)vp,
-                                               [](const GpuView& g) { return g.vpoint_offset; });
-        const GpuView& V = views[v];
-        const int x0 = anc_x0(r.anc), y0 = anc_y0(r.anc);
+        int64_t pix = pix0, W = W0;
+        if (n_views != 1) {
+            const GpuView& V = views[find_view(views, n_views, (int64_t)vp,
+                                               [](const GpuView& g) { return g.vpoint_offset; })];
+            pix = V.pixel_offset;
+            W = V.W;
+        }
+        const int x0 = anc_x0(anc[i]), y0 = anc_y0(anc[i]);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!((mask >> c) & 1u)) continue;
-            const int64_t q = V.pixel_offset + (int64_t)(y0 + (c >> 1)) * V.W + (x0 + (c & 1));
+            const int64_t q = pix + (int64_t)(y0 + (c >> 1)) * W + (x0 + (c & 1));
             s_key[pos] = (uint32_t)q;
             s_id[pos] = 4u * vp + (uint32_t)c;
             ++pos;
@@ -316,7 +330,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_write(
     }
 }
 
-void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
+void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const uint32_t* anc_sorted, const GpuView* views,
                  int n_views, int64_t n_vp, uint32_t* chunk_cnt, uint32_t* m_dev, uint32_t* pkey,
                  uint32_t* pid, uint32_t* clear, size_t clear_words, hipStream_t s) {
     const size_t chunks = emit_chunks(n_vp);
@@ -329,7 +343,7 @@ void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const Poin
                        n_vp, n_live, chunk_cnt, clear, clear_words);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, 0u);
     hipLaunchKernelGGL(k_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       rec, views, n_views, n_vp, n_live, chunk_cnt, pkey, pid);
+                       anc_sorted, views, n_views, n_vp, n_live, chunk_cnt, pkey, pid);
 }
 
 // Tile entries: one (tile, view point) pair per distinct square tile of
@@ -337,7 +351,7 @@ void launch_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const Poin
 // splats touch, written in the order of the depth-sorted points
 // (tiles of one point in ascending corner order of first appearance).
 __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
-    const uint32_t* __restrict__ zval, const PointRec* __restrict__ rec,
+    const uint32_t* __restrict__ zval, const uint32_t* __restrict__ zanc,
     const GpuView* __restrict__ views, int n_views, int64_t n_vp, const uint32_t* __restrict__ n_live, int lg,
     const uint32_t* __restrict__ chunk_off, uint32_t* __restrict__ tkey,
     uint32_t* __restrict__ tval) {
@@ -346,33 +360,43 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     __shared__ uint32_t s_id[4 * kChunk];
     const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
-    uint32_t vals[kEmitItems];
+    uint32_t vals[kEmitItems], anc[kEmitItems];
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
-        vals[i] = (base + i < live) ? zval[base + i] : 0u;
+        const bool in = base + i < live;
+        vals[i] = in ? zval[base + i] : 0u;
+        anc[i] = in ? zanc[base + i] : 0u;
         cnt += vals[i] >> 28;
     }
     uint32_t total;
     uint32_t pos = block_excl_sum<kEmitBlock>(cnt, total, s_tmp);
+    // each item's tile placement is read once (for one view, once per thread)
+    int64_t toff0 = 0, tpr0 = 0;
+    if (n_views == 1) {
+        toff0 = views[0].tile_offset;
+        tpr0 = views[0].tiles_x;
+    }
 #pragma unroll
     for (int i = 0; i < kEmitItems; ++i) {
         if ((vals[i] >> 28) == 0u) continue;
         const uint32_t vp = vals[i] & kVpMask;
-        const PointRec r = rec[vp];
-        const int v = n_views == 1 ? 0
-                                   : find_view(views, n_views, (int64_t)vp,
-                                               [](const GpuView& g) { return g.vpoint_offset; });
-        const GpuView& V = views[v];
-        const int x0 = anc_x0(r.anc), y0 = anc_y0(r.anc);
-        const uint32_t mask = anc_mask(r.anc);
+        int64_t toff = toff0, tpr = tpr0;
+        if (n_views != 1) {
+            const GpuView& V = views[find_view(views, n_views, (int64_t)vp,
+                                               [](const GpuView& g) { return g.vpoint_offset; })];
+            toff = V.tile_offset;
+            tpr = V.tiles_x;
+        }
+        const int x0 = anc_x0(anc[i]), y0 = anc_y0(anc[i]);
+        const uint32_t mask = anc_mask(anc[i]);
         uint32_t seen[4];
         int n = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!((mask >> c) & 1u)) continue;
             const int tx = (x0 + (c & 1)) >> lg, ty = (y0 + (c >> 1)) >> lg;
-            const uint32_t t = (uint32_t)(V.tile_offset + (int64_t)ty * V.tiles_x + tx);
+            const uint32_t t = (uint32_t)(toff + (int64_t)ty * tpr + tx);
             bool dup = false;
 #pragma unroll
             for (int j = 0; j < 4; ++j) dup |= (j < n) && seen[j] == t;
@@ -391,7 +415,7 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     }
 }
 
-void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const PointRec* rec, const GpuView* views,
+void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const uint32_t* anc_sorted, const GpuView* views,
                       int n_views, int64_t n_vp, int tile_log2, uint32_t* chunk_cnt, uint32_t* m_dev,
                       uint32_t* tkey, uint32_t* tval, uint32_t layout, uint32_t* clear, size_t clear_words,
                       hipStream_t s) {
@@ -406,7 +430,7 @@ void launch_tile_emit(const uint32_t* zval_sorted, const uint32_t* n_live, const
                        n_vp, n_live, chunk_cnt, clear, clear_words);
     hipLaunchKernelGGL(k_scan_chunks, dim3(1), dim3(1024), 0, s, chunk_cnt, chunks, m_dev, layout);
     hipLaunchKernelGGL(k_tile_emit_write, dim3((unsigned)chunks), dim3(kEmitBlock), 0, s, zval_sorted,
-                       rec, views, n_views, n_vp, n_live, tile_log2, chunk_cnt, tkey, tval);
+                       anc_sorted, views, n_views, n_vp, n_live, tile_log2, chunk_cnt, tkey, tval);
 }
 
 }  // namespace inpc

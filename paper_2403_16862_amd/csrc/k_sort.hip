@@ -116,12 +116,16 @@ __global__ __launch_bounds__(kSortBlock) void k_scan_rows(uint32_t* __restrict__
     if (threadIdx.x == 0) totals[blockIdx.x] = running;
 }
 
-template <int D, int ITEMS, bool DROP>
+// MODE 0: (key, value) pairs; 1: a second value per key (ain -> aout) moves
+// with the pair; 2: as 1, and keys equal to drop_key are left out.
+template <int D, int ITEMS, int MODE>
 __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev,
+    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, const uint32_t* __restrict__ ain,
+    uint32_t* __restrict__ aout, const uint32_t* __restrict__ n_dev,
     uint32_t n_bound, int shift, const uint32_t* __restrict__ row_prefix, uint32_t stride,
     const uint32_t* __restrict__ bin_total, uint32_t drop_key, uint32_t* __restrict__ live_out) {
+    constexpr bool DROP = MODE == 2, V2 = MODE >= 1;
     constexpr int BINS = 1 << D;
     constexpr int WAVES = kSortBlock / kWave;
     constexpr int TILE = kSortBlock * ITEMS;
@@ -214,17 +218,30 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         }
     }
     __syncthreads();
+    uint32_t slot[ITEMS];   // LDS slot of each item, ~0u for an item that takes no part
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
         const uint32_t idx = base + it * kWave + lane;
+        slot[it] = ~0u;
         if (idx < n && !(DROP && key[it] == drop_key)) {
             const uint32_t d = (key[it] >> shift) & (BINS - 1);
-            const uint32_t slot = s_start[d] + s_cnt[w][d] + rank[it];
-            s_key[slot] = key[it];
-            s_val[slot] = val[it];
+            slot[it] = s_start[d] + s_cnt[w][d] + rank[it];
+            s_key[slot[it]] = key[it];
+            s_val[slot[it]] = val[it];
         }
     }
     __syncthreads();
+    // V2: the second values are requested now and arrive while the pairs
+    // are written; they then take the value slots in LDS (no extra LDS, so
+    // the occupancy of the pair-only passes is kept).
+    uint32_t a2[V2 ? ITEMS : 1];
+    if constexpr (V2) {
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint32_t idx = base + it * kWave + lane;
+            a2[it] = idx < n ? ain[idx] : 0u;
+        }
+    }
     uint32_t tile_n;
     if constexpr (DROP) tile_n = s_tile_n;
     else tile_n = (n - tile * TILE) < (uint32_t)TILE ? (n - tile * TILE) : (uint32_t)TILE;
@@ -235,12 +252,23 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_downsweep(
         kout[dst] = k;
         vout[dst] = s_val[j];
     }
+    if constexpr (V2) {
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it)
+            if (slot[it] != ~0u) s_val[slot[it]] = a2[it];
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < tile_n; j += kSortBlock) {
+            const uint32_t d = (s_key[j] >> shift) & (BINS - 1);
+            aout[s_dst[d] + (j - s_start[d])] = s_val[j];
+        }
+    }
 }
 
 template <int D, int ITEMS>
 static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout,
-                      const uint32_t* n_dev, int64_t n_bound, int shift, uint32_t* counts,
-                      bool drop, uint32_t drop_key, uint32_t* live_out, hipStream_t s) {
+                      const uint32_t* ain, uint32_t* aout, const uint32_t* n_dev, int64_t n_bound, int shift,
+                      uint32_t* counts, bool drop, uint32_t drop_key, uint32_t* live_out, hipStream_t s) {
     const size_t tiles = tiles_for(ITEMS, n_bound);
     const uint32_t stride = (uint32_t)tiles + 1;
     uint32_t* totals = counts + ((size_t)1 << D) * stride;
@@ -261,19 +289,21 @@ static void sort_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, 
     {
         ProfScope p(kStSortDownsweep, s);
         const size_t grid = (tiles + 8 * kXcdGroup - 1) / (8 * kXcdGroup) * (8 * kXcdGroup);
+        auto go = [&](auto kern, uint32_t* lo) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kSortBlock), 0, s, kin, vin, kout, vout, ain, aout,
+                               n_dev, (uint32_t)n_bound, shift, counts, stride, totals, drop_key, lo);
+        };
         if (drop)
-            hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS, true>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
-                               kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
-                               drop_key, live_out);
+            go(k_radix_downsweep<D, ITEMS, 2>, live_out);
+        else if (ain)
+            go(k_radix_downsweep<D, ITEMS, 1>, nullptr);
         else
-            hipLaunchKernelGGL((k_radix_downsweep<D, ITEMS, false>), dim3((unsigned)grid), dim3(kSortBlock), 0, s,
-                               kin, vin, kout, vout, n_dev, (uint32_t)n_bound, shift, counts, stride, totals,
-                               drop_key, nullptr);
+            go(k_radix_downsweep<D, ITEMS, 0>, nullptr);
     }
 }
 
-using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const uint32_t*,
-                        int64_t, int, uint32_t*, bool, uint32_t, uint32_t*, hipStream_t);
+using PassFn = void (*)(const uint32_t*, const uint32_t*, uint32_t*, uint32_t*, const uint32_t*, uint32_t*,
+                        const uint32_t*, int64_t, int, uint32_t*, bool, uint32_t, uint32_t*, hipStream_t);
 
 static PassFn pass_fn(int digit, int items) {
 #define INPC_CASE(D, I) \
@@ -291,11 +321,13 @@ static PassFn pass_fn(int digit, int items) {
 // (ka, va) -> (kb, vb) -> (ka, va) ...  (kin, vin) may alias (kb, vb).
 // live_out != nullptr: pass 0 leaves out every key equal to drop_key and
 // writes the number of kept keys to *live_out, which bounds the later passes
-// (the sorted result is that many keys long).
+// (the sorted result is that many keys long); it requires a second value
+// per key (ain, alternating aa / ab like the values; three distinct arrays),
+// which is permuted with the pairs.
 void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, const uint32_t* vin,
                        uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                        const uint32_t* n_dev, int64_t n_bound, uint32_t* counts, hipStream_t s,
-                       uint32_t drop_key, uint32_t* live_out) {
+                       uint32_t drop_key, uint32_t* live_out, const uint32_t* ain, uint32_t* aa, uint32_t* ab) {
     const int passes = radix_passes(digit, bits);
     if (n_bound == 0 || passes == 0) {
         // nothing sorted: every key stays where it is (keys to drop included)
@@ -305,15 +337,18 @@ void launch_radix_sort(int digit, int items, int bits, const uint32_t* kin, cons
     PassFn fn = pass_fn(digit, items);
     const uint32_t* ki = kin;
     const uint32_t* vi = vin;
-    uint32_t *ko = ka, *vo = va;
+    const uint32_t* ai = ain;
+    uint32_t *ko = ka, *vo = va, *ao = aa;
     for (int p = 0; p < passes; ++p) {
         const bool drop = p == 0 && live_out != nullptr;
-        fn(ki, vi, ko, vo, p > 0 && live_out ? live_out : n_dev, n_bound, p * digit, counts, drop, drop_key,
-           drop ? live_out : nullptr, s);
+        fn(ki, vi, ko, vo, ai, ai ? ao : nullptr, p > 0 && live_out ? live_out : n_dev, n_bound, p * digit, counts,
+           drop, drop_key, drop ? live_out : nullptr, s);
         ki = ko;
         vi = vo;
+        ai = ai ? ao : nullptr;
         ko = (ko == ka) ? kb : ka;
         vo = (vo == va) ? vb : va;
+        ao = (ao == aa) ? ab : aa;
     }
 }
 
