@@ -52,7 +52,8 @@ KERNEL_STAGE = {
     "k_scan_chunks": "emit", "k_radix_upsweep": "sort_upsweep", "k_scan_rows": "sort_scan",
     "k_radix_downsweep": "sort_downsweep", "k_ranges": "ranges", "k_blend_fwd": "blend_fwd",
     "k_tile_fwd": "blend_fwd", "k_blend_bwd": "blend_bwd", "k_tile_bwd": "blend_bwd",
-    "k_point_reduce": "point_reduce", "k_fill_u32": "fill", "k_upload_views": "views",
+    "k_point_reduce": "point_reduce", "k_point_reduce_q": "point_reduce", "k_fill_u32": "fill",
+    "k_upload_views": "views",
     "k_order_hist": "ranges", "k_order_scan": "ranges", "k_order_place": "ranges",
 }
 # copies the runtime makes outside the timed steps (input upload, the counter calibration)
@@ -124,6 +125,8 @@ def summarize_counters(fetch_csv, write_csv):
     for k in sorted(fk, key=lambda k: -sum(fk[k]) / len(fk[k])):
         short = k.split("<")[0].replace("inpc::", "")
         if short not in KERNEL_STAGE:
+            if k.startswith("inpc::"):
+                raise ValueError(f"kernel {k} has no stage in KERNEL_STAGE")
             continue
         f = sum(fk[k]) / len(fk[k]) * fs * 1024
         w = sum(wk[k]) / len(wk[k]) * ws * 1024 if k in wk else 0.0
