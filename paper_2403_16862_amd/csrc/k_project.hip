@@ -103,6 +103,49 @@ __device__ __forceinline__ void project_point(const GpuView& V, float x, float y
     zbits = __float_as_uint(zc);
 }
 
+// One block's run of payload rows (CPR 16-byte pieces per row, 256 rows):
+// thread t writes piece t % CPR of rows t / CPR, t / CPR + 256 / CPR, ...
+// All of the thread's feature pieces are requested before the first store,
+// and unconditionally (a padding piece, or a row without splats, reads a
+// real piece of its row, or of feature row 0, and drops it), so that the
+// thread waits on one memory latency instead of one per row.
+template <int CPR>
+__device__ __forceinline__ void payload_run(uint4* __restrict__ dst, const PointRec* s_rec, const int64_t* s_row,
+                                            int rows, const unsigned char* __restrict__ feat, int frow) {
+    static_assert(CPR == 4 || CPR == 8, "pieces per payload row");
+    constexpr int RSTEP = 256 / CPR;
+    const int fcs = frow / 16;   // feature pieces per row (>= 1)
+    const int col = (int)threadIdx.x % CPR, row0 = (int)threadIdx.x / CPR;
+    const int fc = col < 1 ? 1 : (col > fcs ? fcs : col);
+    auto ld = [&](int k) -> uint4 {
+        const int row = row0 + k * RSTEP;
+        const int64_t ar = row < rows ? s_row[row] : -1;
+        return reinterpret_cast<const uint4*>(feat + (size_t)(ar >= 0 ? ar : 0) * frow)[fc - 1];
+    };
+    auto st = [&](int k, uint4 g) {
+        const int row = row0 + k * RSTEP;
+        if (row < rows && s_row[row] >= 0) {
+            // selects on values (a select of addresses would put g in private memory)
+            const PointRec rr = s_rec[row];
+            const bool pad = col > fcs, rec = col == 0;
+            uint4 v;
+            v.x = rec ? __float_as_uint(rr.ax) : (pad ? 0u : g.x);
+            v.y = rec ? __float_as_uint(rr.ay) : (pad ? 0u : g.y);
+            v.z = rec ? __float_as_uint(rr.opa) : (pad ? 0u : g.z);
+            v.w = rec ? rr.anc : (pad ? 0u : g.w);
+            dst[row * CPR + col] = v;
+        }
+    };
+    // named values rather than an array, which the compiler would keep in scratch
+    const uint4 g0 = ld(0), g1 = ld(1), g2 = ld(2), g3 = ld(3);
+    if constexpr (CPR == 8) {
+        const uint4 g4 = ld(4), g5 = ld(5), g6 = ld(6), g7 = ld(7);
+        st(0, g0); st(1, g1); st(2, g2); st(3, g3); st(4, g4); st(5, g5); st(6, g6); st(7, g7);
+    } else {
+        st(0, g0); st(1, g1); st(2, g2); st(3, g3);
+    }
+}
+
 // Depth keys are float32 bits of z minus the bits of the smallest near
 // plane (z > near >= 0 and bits are monotone there), so they need only as
 // many bits as the (near, far) range spans; points without splats get
@@ -161,7 +204,11 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
             if (col <= fcs) return reinterpret_cast<const uint4*>(feat + (size_t)s_row[row] * frow)[col - 1];
             return make_uint4(0u, 0u, 0u, 0u);
         };
-        if ((256 % cpr) == 0) {
+        if (cpr == 4) {
+            payload_run<4>(dst, s_rec, s_row, rows, feat, frow);
+        } else if (cpr == 8) {
+            payload_run<8>(dst, s_rec, s_row, rows, feat, frow);
+        } else if ((256 % cpr) == 0) {
             const int col = threadIdx.x % cpr, rstep = 256 / cpr;
             for (int row = threadIdx.x / cpr; row < rows; row += rstep)
                 if (s_row[row] >= 0) dst[row * cpr + col] = piece(row, col);
