@@ -166,17 +166,26 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ xyz,
     const int64_t vp = vp0 + threadIdx.x;
     int64_t arow = -1;
     PointRec r{};
-    if (vp < n_vp) {
-        const int v = n_views == 1 ? 0
-                                   : find_view(views, n_views, vp,
-                                               [](const GpuView& g) { return g.vpoint_offset; });
-        const GpuView& V = views[v];
+    // In a batch, the block's view is looked up once (uniform, scalar
+    // loads); a block that straddles two views searches per thread.  (With
+    // one view the per-thread form measures a little faster.)
+    auto vstart = [](const GpuView& g) { return g.vpoint_offset; };
+    const int v0 = n_views == 1 ? 0 : find_view(views, n_views, vp0, vstart);
+    const bool one_view = n_views > 1 && vp0 + 256 <= views[v0].vpoint_offset + views[v0].point_count;
+    auto point = [&](const GpuView& V) {
         const int64_t p = V.point_offset + (vp - V.vpoint_offset);
+        arow = V.attr_offset + (vp - V.vpoint_offset);
         const float x = xyz[3 * p], y = xyz[3 * p + 1], z = xyz[3 * p + 2];
+        const float o = opacity[arow];
         uint32_t zb;
         project_point(V, x, y, z, r, zb);
-        arow = V.attr_offset + (vp - V.vpoint_offset);
-        r.opa = opacity[arow];
+        r.opa = o;
+        return zb;
+    };
+    if (vp < n_vp) {
+        uint32_t zb;
+        if (one_view) zb = point(views[v0]);
+        else zb = point(views[n_views == 1 ? 0 : find_view(views, n_views, vp, vstart)]);
         rec[vp] = r;
         zkey[vp] = r.anc != 0u ? zb - zbase : zkey_none;
         const uint32_t m = anc_mask(r.anc);
@@ -245,6 +254,8 @@ void launch_project(const float* xyz, const float* opa, const GpuView* views, in
 }
 
 // ----------------------------------------------------------------- emission
+constexpr int kLdsViews = 64;   // views whose tile placement the tile emission keeps in LDS
+
 // Fragments are emitted in the order of the depth-sorted points, corners in
 // ascending order, so the emitted sequence is ordered by (depth, splat id).
 // Count -> exclusive scan of chunk counts -> order-preserving write.  Each
@@ -405,6 +416,19 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
     __shared__ uint32_t s_tmp[kEmitBlock / kWave];
     __shared__ uint32_t s_key[4 * kChunk];
     __shared__ uint32_t s_id[4 * kChunk];
+    // A batch's depth-sorted points come from every view, so each item looks
+    // its view up: for up to kLdsViews views in a copy of their tile
+    // placement in LDS (read after the scan's barriers), which waits far less
+    // than a search through memory.
+    __shared__ int64_t s_vstart[kLdsViews], s_toff[kLdsViews], s_tpr[kLdsViews];
+    const bool lds_views = n_views > 1 && n_views <= kLdsViews;
+    if (lds_views) {
+        for (int i = threadIdx.x; i < n_views; i += kEmitBlock) {
+            s_vstart[i] = views[i].vpoint_offset;
+            s_toff[i] = views[i].tile_offset;
+            s_tpr[i] = views[i].tiles_x;
+        }
+    }
     const int64_t live = live_points(n_live, n_vp);
     const int64_t base = (int64_t)blockIdx.x * kChunk + (int64_t)threadIdx.x * kEmitItems;
     uint32_t vals[kEmitItems], anc[kEmitItems];
@@ -429,7 +453,15 @@ __global__ __launch_bounds__(kEmitBlock) void k_tile_emit_write(
         if ((vals[i] >> 28) == 0u) continue;
         const uint32_t vp = vals[i] & kVpMask;
         int64_t toff = toff0, tpr = tpr0;
-        if (n_views != 1) {
+        if (lds_views) {
+            int lo = 0, hi = n_views - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_vstart[mid] <= (int64_t)vp) lo = mid; else hi = mid - 1;
+            }
+            toff = s_toff[lo];
+            tpr = s_tpr[lo];
+        } else if (n_views != 1) {
             const GpuView& V = views[find_view(views, n_views, (int64_t)vp,
                                                [](const GpuView& g) { return g.vpoint_offset; })];
             toff = V.tile_offset;

@@ -18,18 +18,29 @@ __global__ __launch_bounds__(256) void k_point_reduce(
     const float2* __restrict__ frec, const float* __restrict__ g_img, int Fd,
     float* __restrict__ grad_feat, float* __restrict__ grad_opa, float* __restrict__ blend_weight) {
     const int64_t vp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (vp >= n_vp) return;
     // The point's record, its four splat records (zero where nothing was
     // blended) and its view's placement are read together, and for narrow
     // rows the gradient rows of all corners are in flight before the first
     // one is used: each point waits on two memory latencies, not one per
     // read.  No load sits under a branch (a point without splats reads its
     // view's first pixel row and ignores it), so the compiler cannot sink the
-    // record loads behind the wait for the point record.
-    const int v = n_views == 1 ? 0
-                               : find_view(views, n_views, vp, [](const GpuView& g) { return g.vpoint_offset; });
-    const int64_t pix0 = views[v].pixel_offset;
-    const int64_t W = views[v].W;
+    // record loads behind the wait for the point record.  The block's view
+    // is looked up once (uniform); a block across two views searches per
+    // thread.
+    auto vstart = [](const GpuView& g) { return g.vpoint_offset; };
+    const int64_t vpb = (int64_t)blockIdx.x * blockDim.x;
+    const int v0 = n_views == 1 ? 0 : find_view(views, n_views, vpb, vstart);
+    const bool one_view = n_views == 1 || vpb + (int64_t)blockDim.x <= views[v0].vpoint_offset + views[v0].point_count;
+    if (vp >= n_vp) return;
+    int64_t pix0, W;
+    if (one_view) {
+        pix0 = views[v0].pixel_offset;
+        W = views[v0].W;
+    } else {
+        const int v = find_view(views, n_views, vp, vstart);
+        pix0 = views[v].pixel_offset;
+        W = views[v].W;
+    }
     const PointRec pr = rec[vp];
     const float4 r01 = reinterpret_cast<const float4*>(frec)[2 * vp];
     const float4 r23 = reinterpret_cast<const float4*>(frec)[2 * vp + 1];
@@ -106,11 +117,21 @@ __global__ __launch_bounds__(256) void k_point_reduce_q(
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t vp = t / S;
     const int sub = (int)(t % S);
+    // the block's view once (uniform); a block across two views searches per thread
+    auto vstart = [](const GpuView& g) { return g.vpoint_offset; };
+    const int64_t vpb = (int64_t)blockIdx.x * (256 / S);
+    const int v0 = n_views == 1 ? 0 : find_view(views, n_views, vpb, vstart);
+    const bool one_view = n_views == 1 || vpb + 256 / S <= views[v0].vpoint_offset + views[v0].point_count;
     if (vp >= n_vp) return;
-    const int v = n_views == 1 ? 0
-                               : find_view(views, n_views, vp, [](const GpuView& g) { return g.vpoint_offset; });
-    const int64_t pix0 = views[v].pixel_offset;
-    const int64_t W = views[v].W;
+    int64_t pix0, W;
+    if (one_view) {
+        pix0 = views[v0].pixel_offset;
+        W = views[v0].W;
+    } else {
+        const int v = find_view(views, n_views, vp, vstart);
+        pix0 = views[v].pixel_offset;
+        W = views[v].W;
+    }
     const PointRec pr = rec[vp];
     const float4 r01 = reinterpret_cast<const float4*>(frec)[2 * vp];
     const float4 r23 = reinterpret_cast<const float4*>(frec)[2 * vp + 1];
