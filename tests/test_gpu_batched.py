@@ -89,6 +89,18 @@ def test_batched_uneven_views_f32():
     _check_batched(xyz, feat, opa, cams, offs, counts)
 
 
+@pytest.mark.parametrize("n_views", [40, 70])
+def test_batched_many_small_views(n_views):
+    """Up to 64 views the tile emission looks views up in an LDS copy of
+    their placement, past that in memory; view points are not aligned to
+    blocks, so blocks across two views take the per-thread lookups."""
+    rng = np.random.default_rng(100 + n_views)
+    sizes = [(int(rng.integers(8, 65)), int(rng.integers(8, 49))) for _ in range(n_views)]
+    counts = [int(rng.integers(200, 3000)) for _ in range(n_views)]
+    xyz, feat, opa, cams, offs, counts = _views_scene(100 + n_views, sizes, counts)
+    _check_batched(xyz, feat, opa, cams, offs, counts)
+
+
 def test_batched_bf16_and_other_shapes():
     sizes = [(120, 90), (57, 33), (200, 11)]
     counts = [40000, 9000, 15000]
