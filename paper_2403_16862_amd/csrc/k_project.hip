@@ -316,14 +316,26 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit_count(const uint32_t* __res
 // fragment count M) to m_dev[0] and the layout code of the lists to m_dev[1].
 __global__ __launch_bounds__(1024) void k_scan_chunks(uint32_t* __restrict__ cnt, size_t n,
                                                       uint32_t* __restrict__ m_dev, uint32_t layout) {
+    // 8 consecutive counts per thread, so that one round (two barriers)
+    // covers 8192 chunks (8M view points) instead of 1024
+    constexpr int K = 8;
     __shared__ uint32_t s_tmp[1024 / kWave];
     uint32_t running = 0;
-    for (size_t base = 0; base < n; base += 1024) {
-        const size_t i = base + threadIdx.x;
-        const uint32_t x = i < n ? cnt[i] : 0u;
+    for (size_t base = 0; base < n; base += 1024 * K) {
+        const size_t i0 = base + (size_t)threadIdx.x * K;
+        uint32_t x[K], sum = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            x[k] = i0 + k < n ? cnt[i0 + k] : 0u;
+            sum += x[k];
+        }
         uint32_t total;
-        const uint32_t ex = block_excl_sum<1024>(x, total, s_tmp);
-        if (i < n) cnt[i] = running + ex;
+        uint32_t ex = running + block_excl_sum<1024>(sum, total, s_tmp);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (i0 + k < n) cnt[i0 + k] = ex;
+            ex += x[k];
+        }
         running += total;
     }
     if (threadIdx.x == 0) {

@@ -454,12 +454,21 @@ __global__ __launch_bounds__(256) void k_order_place(const uint2* __restrict__ r
         local = atomicAdd(&h[c], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t start = 0;   // classes from the largest down
-        for (int k = kOrderClasses - 1; k >= 0; --k) {
-            base[k] = h[k] ? start + atomicAdd(&cls_next[k], h[k]) : 0u;
-            start += cls_cnt[k];
+    // Lane k of the first wave serves class k: the reservations are issued
+    // together (one round trip, not one per class), and class k starts
+    // after all larger classes (a suffix sum of the class counts).
+    if (threadIdx.x < kWave) {
+        const int k = threadIdx.x;
+        const bool cls = k < kOrderClasses;
+        const uint32_t mine = cls ? h[k] : 0u;
+        const uint32_t got = mine ? atomicAdd(&cls_next[k], mine) : 0u;
+        uint32_t suf = cls ? cls_cnt[k] : 0u;   // inclusive suffix sum over classes >= k
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_down(suf, d);
+            if (k + d < kWave) suf += o;
         }
+        if (cls) base[k] = mine ? (suf - cls_cnt[k]) + got : 0u;
     }
     __syncthreads();
     if (t < n_tiles) perm[base[c] + local] = (uint32_t)t;
