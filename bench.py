@@ -568,7 +568,8 @@ def cpu_leg(pr, torch, np, s, x, f, o, step, log):
 
 def bench_config2(pr, torch, np, workloads, log, reps=20):
     """1M points, 1280x720, F=8 float32, forward + backward through the plain
-    one-view entry points; median of 20 event-timed steps."""
+    one-view entry points, with the autotuner's choice (forward + backward)
+    and with the default tuning; median of 20 event-timed steps each."""
     t0 = time.time()
     s = workloads.config2()
     log(f"generated config 2 in {time.time() - t0:.1f}s: N={s.n} {s.cam.width}x{s.cam.height} F={s.F}")
@@ -578,18 +579,22 @@ def bench_config2(pr, torch, np, workloads, log, reps=20):
     o = torch.from_numpy(s.opa).to(dev)
     g = torch.from_numpy(s.g_img).to(dev)
 
-    def fb():
-        img, tf, st = pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save")
+    tid, _ = pr.autotune(x, f, o, pr.make_views([s.cam], [0], [s.n]), g_img=g, repeats=1)
+
+    def fb(t):
+        img, tf, st = pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save", t)
         pr.rasterize_backward(x, f, o, st, g)
 
-    ms = event_ms(torch, fb, reps=reps)
-    ms_f = event_ms(torch, lambda: pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save"), reps=reps)
-    _, _, st = pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save", keep_workspace=True)
+    ms = event_ms(torch, lambda: fb(tid), reps=reps)
+    ms_default = event_ms(torch, lambda: fb(0), reps=reps)
+    ms_f = event_ms(torch, lambda: pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save", tid), reps=reps)
+    _, _, st = pr.rasterize_forward(x, f, o, s.cam, 1e-4, "save", tid, keep_workspace=True)
     M = pr.fragment_count(st)
     out = {"workload": "1M clustered points (64 clusters), 1280x720, F=8 float32, forward+backward through "
                        "inpc_rasterize_fwd / inpc_rasterize_bwd",
            "points": s.n, "fragments": M, "ms_fwd_bwd": round(ms, 4), "ms_fwd": round(ms_f, 4),
-           "fragments_per_s": round(M / (ms * 1e-3), 1)}
+           "fragments_per_s": round(M / (ms * 1e-3), 1), "tuning": tid,
+           "ms_fwd_bwd_default_tuning": round(ms_default, 4)}
     log(f"config 2: {json.dumps(out)}")
     return out
 
