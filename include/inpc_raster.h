@@ -29,6 +29,9 @@
  *     error nothing is enqueued and a negative INPC_E* code is returned.
  *     Per-element preconditions (opacity in [0,1], finite features) are not
  *     checked.
+ *   - Environment: INPC_LOG set (and not "0") makes every rasterizing call
+ *     print one line on stderr: the tuning, list layout and sort digits and
+ *     passes it chose, or why it was rejected.  It is read at each call.
  *   - Layouts: xyz float32 [N,3] row-major; features [N,F] row-major in
  *     float32 or bfloat16 (``feat_dtype``); opacity float32 [N] (the activated
  *     alpha_h); image float32 [H,W,F]; t_final float32 [H,W] (the remaining

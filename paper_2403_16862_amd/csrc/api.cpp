@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -486,6 +487,35 @@ static void build_fragments(const Problem& pb, const Tuning& tn, const float* xy
     }
 }
 
+// ------------------------------------------------------------- logging
+// INPC_LOG set (and not "0"): every rasterizing call reports on stderr the
+// choices it made (tuning, list layout, sort digits and passes) or why it
+// was rejected.  Read at each call, so it can be switched in a running process.
+static bool log_on() {
+    const char* e = std::getenv("INPC_LOG");
+    return e && e[0] && std::strcmp(e, "0") != 0;
+}
+
+static void log_choices(const char* what, const Problem& pb, int tid, int shape) {
+    if (!log_on()) return;
+    const Tuning& tn = kTunings[tid];
+    const bool tile = is_tile_shape(shape);
+    const int kbits = tile ? pb.tile_bits : pb.pixel_bits;
+    const int zd = zdigit_of(tn, pb.zbits), kd = pdigit_of(tn, kbits);
+    std::fprintf(stderr,
+                 "inpc: %s: %zu view(s), %lld view points, %lld pixels, F=%d %s, %s mode; tuning %d (%s); "
+                 "depth sort %d bits = %d pass(es) of %d; %s sort %d bits = %d pass(es) of %d, %d-key tiles\n",
+                 what, pb.views.size(), (long long)pb.n_vp, (long long)pb.n_pixels, pb.F,
+                 pb.fdt == INPC_BF16 ? "bfloat16" : "float32", pb.mode == INPC_SAVE ? "save" : "recompute", tid,
+                 tn.name, pb.zbits, radix_passes(zd, pb.zbits), zd, tile ? "tile" : "pixel", kbits,
+                 radix_passes(kd, kbits), kd, 512 * tn.sort_items);
+}
+
+static int log_rejected(const char* what, int rc) {
+    if (rc != INPC_OK && log_on()) std::fprintf(stderr, "inpc: %s rejected: %s\n", what, inpc_error_string(rc));
+    return rc;
+}
+
 // ------------------------------------------------------------- forward
 static int forward(const Problem& pb, int tid, const float* xyz, const void* feat,
                    const float* opacity, float tau, float* image, float* t_final, float* blend_weight,
@@ -494,6 +524,7 @@ static int forward(const Problem& pb, int tid, const float* xyz, const void* fea
     if (saved_bytes < L.saved_bytes || ws_bytes < L.fwd_bytes) return INPC_EWORKSPACE;
     if (pb.n_pixels > 0 && (!saved || !ws)) return INPC_EINVAL;
     const Tuning& tn = kTunings[tid];
+    log_choices("forward", pb, tid, tn.blend_shape);
     uint32_t* m_dev = at<uint32_t>(saved, L.s_scalars);
     void* frag_base = pb.mode == INPC_SAVE ? saved : ws;
     const FragOffsets& fo = pb.mode == INPC_SAVE ? L.saved_frag : L.fwd_frag;
@@ -540,6 +571,7 @@ static int backward(const Problem& pb, int tid, float tau, const float* xyz, con
     const FragOffsets* fo;
     const GpuView* views;
     const int bshape = bwd_shape_of(tid, pb.mode);
+    log_choices("backward", pb, tid, bshape);
     if (pb.mode == INPC_SAVE) {
         // The forward left its device view table in the saved state; its tile
         // grid is the forward blend's, so a backward blend with other block
@@ -641,10 +673,10 @@ static int sizes_impl(const inpc_view_t* views, int n_views, int64_t n_points, i
     return INPC_OK;
 }
 
-static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
-                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
-                    float* image, float* t_final, float* blend_weight, void* saved, size_t saved_bytes,
-                    void* ws, size_t ws_bytes, void* stream) {
+static int fwd_checked(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                       int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                       float* image, float* t_final, float* blend_weight, void* saved, size_t saved_bytes,
+                       void* ws, size_t ws_bytes, void* stream) {
     int treq, mode;
     float tau;
     bool avp;
@@ -671,6 +703,14 @@ static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     record_saved_tuning(saved, tid);
     return forward(pb, tid, xyz, feat, opa, tau, image, t_final, blend_weight, saved, saved_bytes, ws,
                    ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+static int fwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                    float* image, float* t_final, float* blend_weight, void* saved, size_t saved_bytes,
+                    void* ws, size_t ws_bytes, void* stream) {
+    return log_rejected("forward", fwd_checked(xyz, feat, fdt, opa, n_points, F, views, n_views, st, image, t_final,
+                                               blend_weight, saved, saved_bytes, ws, ws_bytes, stream));
 }
 
 // ------------------------------------------------------------ multisampling
@@ -757,11 +797,11 @@ static int ms_impl(const float* xyz, const void* feat, int fdt, const float* opa
     return check_launch("inpc multisample");
 }
 
-static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
-                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
-                    const void* saved, size_t saved_bytes, const float* g_img, const float* g_t,
-                    float* grad_feat, float* grad_opa, float* blend_weight, void* ws, size_t ws_bytes,
-                    void* stream) {
+static int bwd_checked(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                       int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                       const void* saved, size_t saved_bytes, const float* g_img, const float* g_t,
+                       float* grad_feat, float* grad_opa, float* blend_weight, void* ws, size_t ws_bytes,
+                       void* stream) {
     int treq, mode;
     float tau;
     bool avp;
@@ -787,6 +827,16 @@ static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* op
     if ((saved && !aligned(saved, 256)) || (ws && !aligned(ws, 256))) return INPC_EINVAL;
     return backward(pb, tid, tau, xyz, feat, opa, saved, saved_bytes, g_img, g_t, grad_feat, grad_opa,
                     blend_weight, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+static int bwd_impl(const float* xyz, const void* feat, int fdt, const float* opa, int64_t n_points,
+                    int F, const inpc_view_t* views, int n_views, const inpc_settings_t* st,
+                    const void* saved, size_t saved_bytes, const float* g_img, const float* g_t,
+                    float* grad_feat, float* grad_opa, float* blend_weight, void* ws, size_t ws_bytes,
+                    void* stream) {
+    return log_rejected("backward", bwd_checked(xyz, feat, fdt, opa, n_points, F, views, n_views, st, saved,
+                                                saved_bytes, g_img, g_t, grad_feat, grad_opa, blend_weight, ws,
+                                                ws_bytes, stream));
 }
 
 }  // namespace inpc

@@ -121,6 +121,20 @@ def test_forward_rejects_unknown_flags():
     assert _fwd(st=st) == -1
 
 
+def test_inpc_log_reports_rejected_calls(capfd, monkeypatch):
+    """INPC_LOG set: a rejected call says so on stderr (the line a launched
+    call prints with its tuning and sort passes needs a GPU)."""
+    monkeypatch.delenv("INPC_LOG", raising=False)
+    assert _fwd(ws_bytes=16) == -2
+    assert "inpc:" not in capfd.readouterr().err
+    monkeypatch.setenv("INPC_LOG", "1")
+    assert _fwd(ws_bytes=16) == -2
+    assert "inpc: forward rejected: workspace or saved buffer too small" in capfd.readouterr().err
+    monkeypatch.setenv("INPC_LOG", "0")
+    assert _fwd(ws_bytes=16) == -2
+    assert "inpc:" not in capfd.readouterr().err
+
+
 def test_forward_rejects_null_and_misaligned():
     assert _fwd(image=None) == -1
     assert _fwd(image=FAKE + 4) == -1       # image must be 16-byte aligned
