@@ -174,17 +174,18 @@ def compulsory_bytes(N, N_vis, M, M_b, P, F, feat_bytes, zpasses, ppasses, paylo
     once, each output written once).  Per-pixel lists store and sort the M
     splats; tile lists store and sort E tile entries with one range per tile
     and read each visible point's payload row (16-byte record + features,
-    written by the projection)."""
+    written by the projection).  The depth passes carry each point's anchor
+    word beside its key and value, and the emission reads it in sorted order."""
     items = M if E is None else E        # list items emitted, sorted and read by the blends
     blended = M_b if E is None else E    # list items a blend reads
     R = P if E is None else n_tiles      # ranges
     row = 16 + F * feat_bytes
     payload = payload_stride * N_vis if E is not None else 0
     return {
-        "project": 12 * N + 4 * N + 16 * N + 8 * N + payload,
+        "project": 12 * N + 4 * N + 16 * N + 12 * N + payload,
         "sort_upsweep": zpasses * 4 * N + ppasses * 4 * items,
-        "sort_downsweep": zpasses * 16 * N + ppasses * 16 * items,
-        "emit": 4 * N + 4 * N + 16 * N_vis + 8 * items,
+        "sort_downsweep": zpasses * 24 * N + ppasses * 16 * items,
+        "emit": 4 * N + 8 * N + 8 * items,
         "ranges": 8 * R + 4 * items,
         "blend_fwd": 8 * R + 4 * blended + row * N_vis + (4 * F + 4 + 16) * P + 4 * M_b,
         "clear_records": 32 * N,
