@@ -103,6 +103,25 @@ def test_everything_culled():
     assert lists.m == 0
 
 
+def test_non_finite_positions_are_culled():
+    """Points with NaN or infinite coordinates fail the depth or image test
+    of the projection (every comparison with NaN is false) and emit nothing;
+    the rest are rasterized as usual."""
+    cam = workloads.canonical_camera(40, 30)
+    rng = np.random.default_rng(4)
+    n = 3000
+    xyz = workloads.scenes.cluster_points(rng, n, 4, cam).astype(np.float32)
+    xyz[::17, 0] = np.nan
+    xyz[5::19, 1] = np.inf
+    xyz[7::23, 2] = -np.inf
+    xyz[9::29, 2] = np.nan
+    feat = rng.uniform(0, 1, (n, 4)).astype(np.float32)
+    opa = rng.uniform(0.05, 0.95, n).astype(np.float32)
+    run, lists, n_gpu = _scene_case(xyz, feat, opa, cam)
+    bad = ~np.isfinite(xyz).all(1)
+    assert lists.m > 0 and not np.isin(np.nonzero(bad)[0], lists.ids >> 2).any()
+
+
 def test_pixel_centres_duplicates_and_opaque_points():
     W, Hh = 32, 24
     cam = workloads.Camera(R=np.eye(3, dtype=np.float32), t=np.zeros(3, np.float32), fx=1.0, fy=1.0,
