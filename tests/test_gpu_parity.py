@@ -122,6 +122,28 @@ def test_non_finite_positions_are_culled():
     assert lists.m > 0 and not np.isin(np.nonzero(bad)[0], lists.ids >> 2).any()
 
 
+def test_inpc_log_reports_the_choices_of_a_call(capfd, monkeypatch):
+    """INPC_LOG set: a forward and its backward each print their tuning, list
+    layout and sort passes (here the default tuning: 8x8 tile lists, a 27-bit
+    depth key in 3 passes of 9 bits, 2^8 tiles in one pass)."""
+    cam = workloads.canonical_camera(128, 128)
+    rng = np.random.default_rng(8)
+    n = 4000
+    xyz = workloads.scenes.cluster_points(rng, n, 4, cam).astype(np.float32)
+    feat = rng.uniform(0, 1, (n, 4)).astype(np.float32)
+    opa = rng.uniform(0.05, 0.95, n).astype(np.float32)
+    monkeypatch.setenv("INPC_LOG", "1")
+    capfd.readouterr()
+    run = H.gpu_forward(xyz, feat, opa, cam, tuning_id=0)
+    H.gpu_backward(run, np.ones((128 * 128, 4), np.float32))
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("inpc: ")]
+    assert len(lines) == 2 and lines[0].startswith("inpc: forward:") and lines[1].startswith("inpc: backward:")
+    for l in lines:
+        assert f"{n} view points, 16384 pixels, F=4 float32, save mode; tuning 0" in l
+        assert "depth sort 27 bits = 3 pass(es) of 9; tile sort 8 bits = 1 pass(es) of 8" in l
+
+
 def test_pixel_centres_duplicates_and_opaque_points():
     W, Hh = 32, 24
     cam = workloads.Camera(R=np.eye(3, dtype=np.float32), t=np.zeros(3, np.float32), fx=1.0, fy=1.0,
